@@ -1,0 +1,162 @@
+"""Pins for the oracle's network, gradient, compositing and HS baseline."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from synth.configs import get_config
+from synth.weights import SdfNet, ColorNet, sdf_params
+from oracle import field as F
+from oracle import render as Rn
+
+
+def test_softplus_textbook_values():
+    beta = 100.0
+    z = torch.tensor([0.0, 0.5, -0.5, 1e-3, -30.0], dtype=torch.float64)
+    sp = F.softplus_beta(z, beta)
+    assert sp[0].item() == pytest.approx(math.log(2.0) / beta, abs=1e-18)
+    assert sp[1].item() == pytest.approx(0.5 + math.exp(-50) / beta, rel=1e-15)
+    assert sp[2].item() == pytest.approx(math.exp(-50) / beta, rel=1e-12)
+    assert sp[3].item() == pytest.approx(math.log(1 + math.exp(0.1)) / beta, rel=1e-14)
+    assert sp[4].item() == 0.0 or sp[4].item() < 1e-300
+
+
+def test_one_hidden_unit_closed_form_and_gradient():
+    """y0 = softplus_beta(x_hat_0) for a 1-unit network, f = scale * y0:
+    f(center) = scale ln2/beta and df/dx = sigmoid(beta x_hat_0) = 1/2 there."""
+    net = SdfNet(width=1, n_hidden=1, pe_freqs=0, skip_at=-1, n_feat=0, beta=100.0)
+    params = np.array([1.0, 0.0, 0.0, 0.0, 1.0, 0.0], np.float32)  # W0=[1,0,0], b0, W1=[1], b1
+    layers = F.as_layers(params, net.layer_dims())
+    scale = 2.0
+    p = torch.tensor([[0.0, 0.3, -0.2], [1.0, 0.0, 0.0]], dtype=torch.float64, requires_grad=True)
+    f, feat, _ = F.sdf_forward(net, layers, p, (0.0, 0.0, 0.0), scale)
+    (g,) = torch.autograd.grad(f.sum(), p)
+    assert f[0].item() == pytest.approx(scale * math.log(2) / 100, rel=1e-15)
+    assert g[0, 0].item() == pytest.approx(0.5, rel=1e-15)
+    assert g[0, 1].item() == 0.0 and g[0, 2].item() == 0.0
+    assert f[1].item() == pytest.approx(scale * (0.5 + math.log1p(math.exp(-50)) / 100), rel=1e-15)
+    assert g[1, 0].item() == pytest.approx(1 / (1 + math.exp(-50)), rel=1e-15)
+
+
+def test_encoding_values():
+    x = torch.tensor([[math.pi / 2, 0.0, math.pi]], dtype=torch.float64)
+    g = F.encode(x, 2)
+    assert g.shape == (1, 15)
+    exp = [math.pi / 2, 0, math.pi, 1, 0, 0, 0, 1, -1, 0, 0, 0, -1, 1, 1]
+    np.testing.assert_allclose(g[0].numpy(), exp, atol=1e-15)
+
+
+@pytest.mark.parametrize("name", ["c1", "c2"])
+def test_gradient_matches_finite_differences(name):
+    cfg = get_config(name)
+    layers = F.as_layers(cfg.sdf_params(), cfg.sdf.layer_dims())
+    rng = np.random.default_rng(0)
+    c = np.asarray(cfg.in_center)
+    p = torch.tensor(c + cfg.in_scale * rng.uniform(-0.8, 0.8, (16, 3)), dtype=torch.float64,
+                     requires_grad=True)
+    f, _, _ = F.sdf_forward(cfg.sdf, layers, p, cfg.in_center, cfg.in_scale)
+    (g,) = torch.autograd.grad(f.sum(), p)
+    eps = 1e-6 * cfg.in_scale
+    with torch.no_grad():
+        for a in range(3):
+            d = torch.zeros(3, dtype=torch.float64)
+            d[a] = eps
+            fp = F.sdf_forward(cfg.sdf, layers, p + d, cfg.in_center, cfg.in_scale)[0]
+            fm = F.sdf_forward(cfg.sdf, layers, p - d, cfg.in_center, cfg.in_scale)[0]
+            fd = (fp - fm) / (2 * eps)
+            np.testing.assert_allclose(g[:, a].numpy(), fd.numpy(), rtol=1e-6, atol=1e-7)
+
+
+@pytest.mark.parametrize("name", ["c1", "c2"])
+def test_geometric_init_is_close_to_a_sphere(name):
+    cfg = get_config(name)
+    rng = np.random.default_rng(1)
+    xh = rng.uniform(-0.9, 0.9, (2000, 3))
+    p = np.asarray(cfg.in_center) + cfg.in_scale * xh
+    f = F.sdf_only(cfg, cfg.sdf_params(), p) / cfg.in_scale
+    r = np.linalg.norm(xh, axis=1)
+    err = f - (r - cfg.sdf.sphere_r)
+    # finite-width networks only approximate the sphere: loose statement
+    assert np.abs(err).mean() < (0.1 if cfg.sdf.width >= 256 else 0.25)
+    assert np.corrcoef(f, r)[0, 1] > (0.9 if cfg.sdf.width >= 256 else 0.5)
+
+
+def _plane_rays(s, n_sec, t0, t1, cos=-1.0, f0=0.7):
+    """One ray through the plane f(t) = f0 + cos t, sections of [t0, t1]."""
+    edges = np.linspace(t0, t1, n_sec + 1)
+    t = 0.5 * (edges[:-1] + edges[1:])
+    dt = np.diff(edges)
+    f = f0 + cos * t
+    v = np.array([[1.0, 0.0, 0.0]], np.float32)
+    grad = np.tile([cos, 0.0, 0.0], (n_sec, 1))
+    rgb = np.tile([0.2, 0.4, 0.6], (n_sec, 1))
+    return edges, t, dt, f, v, grad, rgb
+
+
+def test_composite_plane_telescopes_exactly():
+    s = 64.0
+    edges, t, dt, f, v, grad, rgb = _plane_rays(s, 37, 0.3, 1.1)
+    out = Rn.composite([0, 37], v, t, dt, f, grad, rgb, s)
+    phi = lambda x: 1 / (1 + np.exp(-s * x))
+    fe = 0.7 - edges
+    # contiguous sections telescope: T_k = Phi(f(a_k)) / Phi(f(a_0))
+    assert out["acc"][0] == pytest.approx(1 - phi(fe[-1]) / phi(fe[0]), rel=1e-13)
+    np.testing.assert_allclose(out["w"], (phi(fe[:-1]) - phi(fe[1:])) / phi(fe[0]), rtol=1e-12, atol=1e-15)
+    np.testing.assert_allclose(out["rgb"][0], out["acc"][0] * np.array([0.2, 0.4, 0.6]), rtol=1e-13)
+    np.testing.assert_allclose(out["normal"][0], [-1, 0, 0], atol=1e-15)
+
+
+def test_composite_depth_symmetric_window_is_the_hit():
+    """Cells symmetric about the zero crossing t* give depth exactly t*."""
+    s = 64.0
+    t_star = 0.7
+    edges, t, dt, f, v, grad, rgb = _plane_rays(s, 40, t_star - 0.4, t_star + 0.4)
+    out = Rn.composite([0, 40], v, t, dt, f, grad, rgb, s)
+    assert out["depth"][0] == pytest.approx(t_star, abs=1e-13)
+
+
+def test_composite_dense_full_range_vs_bounded():
+    """Dense brute force over the full range converges to the bounded result."""
+    s = 64.0
+    res = []
+    for t0, t1, n in ((0.0, 10.0, 4096 * 4), (0.45, 0.95, 64)):
+        edges, t, dt, f, v, grad, rgb = _plane_rays(s, n, t0, t1)
+        res.append(Rn.composite([0, n], v, t, dt, f, grad, rgb, s))
+    assert res[0]["acc"][0] == pytest.approx(res[1]["acc"][0], abs=1e-6)
+    assert res[0]["depth"][0] == pytest.approx(res[1]["depth"][0], abs=1e-6)
+
+
+def test_composite_weights_bounded_random():
+    rng = np.random.default_rng(2)
+    R = 50
+    counts = rng.integers(0, 30, R)
+    off = np.concatenate([[0], np.cumsum(counts)])
+    S = off[-1]
+    t = rng.uniform(0, 5, S)
+    dt = rng.uniform(0, 0.2, S)
+    f = rng.normal(0, 0.3, S)
+    grad = rng.normal(size=(S, 3))
+    rgb = rng.uniform(size=(S, 3))
+    v = rng.normal(size=(R, 3)).astype(np.float32)
+    out = Rn.composite(off, v, t, dt, f, grad, rgb, 64.0)
+    assert (out["w"] >= 0).all()
+    assert (out["acc"] <= 1 + 1e-12).all()
+    assert (out["acc"][counts == 0] == 0).all() and (out["depth"][counts == 0] == 0).all()
+
+
+def test_hs_upsample_uniform_weights_are_stratified():
+    z = np.linspace(0.5, 2.0, 64)[None]
+    fine = Rn.hs_upsample(z, np.full((1, 64), 3.0), 64.0, 64)  # far outside: alpha = 0
+    u = (np.arange(64) + 0.5) / 64
+    np.testing.assert_allclose(fine[0], 0.5 + u * 1.5, rtol=0, atol=1e-12)
+
+
+def test_hs_upsample_concentrates_at_the_surface():
+    z = np.linspace(0.0, 4.0, 64)[None]
+    f = 1.3 - z                       # plane crossing at t = 1.3
+    fine = Rn.hs_upsample(z, f, 64.0, 64)
+    assert np.median(fine) == pytest.approx(1.3, abs=4.0 / 63)
+    assert (np.diff(fine[0]) >= 0).all()
+    t, dt = Rn.hs_sections(z, fine, np.array([4.0]))
+    assert (dt >= 0).all() and dt.sum() == pytest.approx(4.0, abs=1e-12)
