@@ -1,0 +1,238 @@
+#!/usr/bin/env python3
+"""Benchmark: rays/s of TSDF-bounded rendering on one MI355X.
+
+Workload (default, "c2"): a 6x6x3 m synthetic room (20 boxes, four 2 cm
+slabs); a 256^3 TSDF fused from 100 seeded 384x384 depth maps (14.7 M rays);
+one 640x480 novel view (307 200 rays); SDF network 8x256 (6-frequency
+encoding, skip at layer 4, 257 outputs) and colour network 4x256, FP32.
+
+A timed step is one TSDF-bounded render of the view with the volume resident:
+Alg. 1 bounds -> adaptive placement -> field (SDF + grad f + colour) ->
+compositing.  Also reported on the same GPU: dense 64+64 hierarchical
+sampling, the BF16 field (when supported), the integration throughput, the
+field kernel's roofline fraction and the CPU oracle on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_TFLOPS = {"f32": 157.3, "bf16": 2500.0}
+HBM_PEAK_GBS = 8000.0
+
+
+def field_flops_per_sample(sdf, col):
+    """Algorithmic FLOP of one full field evaluation: SDF forward, reverse
+    pass for d f / d x (all hidden layers, f row only at the output), colour
+    forward.  Padding and recomputation are not counted."""
+    dims = sdf.layer_dims()
+    fwd = sum(i * o for i, o in dims)
+    rev = dims[-1][0] + sum(i * o for i, o in dims[:-1])
+    colour = sum(i * o for i, o in col.layer_dims())
+    return 2 * (fwd + rev + colour), 2 * fwd
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(cfg, ro, rv, n_rays, seed=0):
+    """The FP64 oracle's render path on a seeded subset of the view's rays,
+    with the oracle's own volume (stored flags written by the oracle)."""
+    import torch
+    from oracle import tsdf as OT, field as OF, render as OR
+    gold = np.load(os.path.join(ROOT, "tests", "golden", f"{cfg.name}_volume.npz"))
+    N = int(gold["n_vox"])
+    f0 = np.unpackbits(gold["flag0"])[:N]
+    f1 = np.unpackbits(gold["flag1"])[:N]
+    fl = (f0 | (f1 << 1)).astype(np.uint8)
+    idx = np.sort(np.random.default_rng(seed).choice(ro.shape[0], n_rays, replace=False))
+    o, v = ro[idx], rv[idx]
+    s = cfg.sampling
+    t0 = time.perf_counter()
+    b = OT.bounds(cfg.grid, fl, o, v, s.t_far)
+    p = OT.place(b["t_n"], b["t_f"], b["n_vox"], b["status"], s.rho_num, s.rho_den, s.n_min, s.n_max)
+    f, g, rgb = OF.eval_samples(cfg, cfg.sdf_params(), cfg.color_params(), o, v, p["t"], p["ray_id"])
+    OR.composite(p["offsets"], v, p["t"], p["dt"], f, g, rgb, cfg.neus_s)
+    dt = time.perf_counter() - t0
+    return dict(value=n_rays / dt, unit="rays/s", cores=torch.get_num_threads(), kind="oracle",
+                sample=f"{n_rays} seeded rays of the view through the FP64 oracle render path "
+                       f"(bounds, placement, field, compositing) with the oracle's stored flags; "
+                       f"{int(p['offsets'][-1])} samples; {dt:.1f} s")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="c2")
+    ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16"])
+    ap.add_argument("--hs-steps", type=int, default=2)
+    ap.add_argument("--cpu-rays", type=int, default=1024)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-hs", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU design is "
+              "described in DESIGN.md but not built", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from synth.configs import get_config
+    from paper_2311_17878_amd import ops, _lib
+    from paper_2311_17878_amd.pipeline import TsdfRenderer
+
+    torch.cuda.set_device(0)
+    cfg = get_config(args.workload)
+    g, s = cfg.grid, cfg.sampling
+    prec = _lib.BF16 if args.precision == "bf16" else _lib.FP32
+    t0 = time.time()
+    o, v, d = cfg.integration_rays()
+    ro, rv = cfg.render_rays()
+    log(f"inputs: {o.shape[0]} training rays, {ro.shape[0]} render rays ({time.time() - t0:.1f} s)")
+    dev = lambda a: torch.as_tensor(np.ascontiguousarray(a)).cuda()
+    grid = ops.make_grid(g.n, g.lo, g.h, g.d_t, g.d_s, g.nb_radius, g.m_consec)
+    field = ops.Field(cfg.sdf.width, cfg.sdf.n_hidden, cfg.sdf.pe_freqs, cfg.sdf.skip_at,
+                      cfg.sdf.n_feat, cfg.color.n_hidden, cfg.sdf.beta, cfg.in_center,
+                      cfg.in_scale, cfg.sdf_params(), cfg.color_params())
+    R = TsdfRenderer(grid, field, s.rho_num, s.rho_den, s.n_min, s.n_max, cfg.neus_s, s.t_far, prec)
+    o_d, v_d, d_d = dev(o), dev(v), dev(d)
+    ro_d, rv_d = dev(ro), dev(rv)
+    n_rays = ro.shape[0]
+
+    # ---- integration throughput (one pass over all training rays, resident)
+    nup = torch.zeros(1, dtype=torch.int64, device="cuda")
+    R.state = ops.new_state(grid)
+    R.integrate(o_d, v_d, d_d, batch=o.shape[0])        # warm-up pass
+    torch.cuda.synchronize()
+    R.state = ops.new_state(grid)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    R.integrate(o_d, v_d, d_d, batch=o.shape[0], n_updates=nup)
+    e1.record()
+    torch.cuda.synchronize()
+    integ_ms = e0.elapsed_time(e1)
+    e0.record()
+    R.finalize()
+    e1.record()
+    torch.cuda.synchronize()
+    fin_ms = e0.elapsed_time(e1)
+    updates = int(nup.item())
+    log(f"integrate: {integ_ms:.2f} ms, {updates} updates; finalize {fin_ms:.2f} ms")
+
+    # ---- TSDF-bounded render: warm-up, then exactly K timed steps
+    for _ in range(args.warmup):
+        R.render(ro_d, rv_d)
+    torch.cuda.synchronize()
+    ev = {}
+    start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    start.record()
+    for _ in range(args.steps):
+        out = R.render(ro_d, rv_d, events=ev)
+    end.record()
+    torch.cuda.synchronize()
+    ms = start.elapsed_time(end) / args.steps
+    stage_ms = {k: float(np.mean([a.elapsed_time(b) for a, b in v_])) for k, v_ in ev.items()}
+    S = int(out["s_total"].item())
+    chk = R.render(ro_d, rv_d, keep=True)
+    counts = chk["place"]["counts"].cpu().numpy()
+    status = chk["bounds"]["status"].cpu().numpy()
+    nz = counts[counts > 0]
+    fl_sample, fl_sdf_only = field_flops_per_sample(cfg.sdf, cfg.color)
+    field_ms = stage_ms["field"]
+    achieved = S * fl_sample / (field_ms * 1e-3) / 1e12
+    dtype = "bf16" if prec == _lib.BF16 else "f32"
+    log(f"render: {ms:.3f} ms/step, {n_rays / ms * 1e3:.0f} rays/s, S={S}, stages {stage_ms}")
+
+    result = {
+        "metric": "rays/sec and samples/ray, TSDF-bounded vs 64+64 hierarchical; BF16 vs FP32",
+        "value": n_rays / (ms * 1e-3),
+        "unit": "rays/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": dtype,
+        "data": "synthetic",
+        "config": {
+            "workload": f"{cfg.name}: one {ro.shape[0]}-ray novel view; {cfg.notes}; "
+                        f"TSDF {g.n[0]}^3, h={g.h:.6f} m, D_T=5h, D_s=1h, 5^3 neighbourhood, M=15; "
+                        f"SDF {cfg.sdf.n_hidden}x{cfg.sdf.width} PE{cfg.sdf.pe_freqs} skip{cfg.sdf.skip_at}, "
+                        f"colour {cfg.color.n_hidden}x{cfg.color.width}; NeuS s={cfg.neus_s:g}",
+            "rays": n_rays,
+            "rho": f"{s.rho_num}/{s.rho_den} samples per traversed voxel",
+            "n_min": s.n_min, "n_max": s.n_max,
+            "precision": dtype,
+        },
+        "samples_per_ray": {
+            "mean": S / n_rays,
+            "mean_nonzero": float(nz.mean()) if nz.size else 0.0,
+            "min": int(counts.min()), "p50": float(np.percentile(counts, 50)),
+            "p99": float(np.percentile(counts, 99)), "max": int(counts.max()),
+            "status_counts": {k: int((status == i).sum()) for i, k in
+                              enumerate(["hit", "no_far", "miss", "invalid"])},
+            "samples": S,
+        },
+        "stage_ms": stage_ms,
+        "roofline": {
+            "kernel": "k_field_fp32" if prec == _lib.FP32 else "k_field_bf16",
+            "bound": "mfma",
+            "achieved": achieved,
+            "peak": PEAK_TFLOPS[dtype],
+            "unit": "TFLOP/s",
+            "frac": achieved / PEAK_TFLOPS[dtype],
+            "traffic": None,
+            "flop_per_sample": fl_sample,
+        },
+        "integrate": {
+            "rays": int(o.shape[0]), "ms": integ_ms, "rays_per_s": o.shape[0] / (integ_ms * 1e-3),
+            "voxel_updates": updates, "updates_per_s": updates / (integ_ms * 1e-3),
+            "finalize_ms": fin_ms,
+            "paper_context": "1.445e6 rays/s (0.692 us/ray, 39.0 M rays in 27.02 s, GPU unnamed)",
+        },
+    }
+
+    if not args.no_hs:
+        for _ in range(1):
+            R.render_hs(ro_d, rv_d)
+        torch.cuda.synchronize()
+        ev_hs = {}
+        start.record()
+        for _ in range(args.hs_steps):
+            R.render_hs(ro_d, rv_d, events=ev_hs)
+        end.record()
+        torch.cuda.synchronize()
+        hs_ms = start.elapsed_time(end) / args.hs_steps
+        result["hs_64_64"] = {
+            "ms_per_step": hs_ms, "rays_per_s": n_rays / (hs_ms * 1e-3), "samples_per_ray": 192,
+            "stage_ms": {k: float(np.mean([a.elapsed_time(b) for a, b in v_]))
+                         for k, v_ in ev_hs.items()},
+            "speedup_tsdf_vs_hs": hs_ms / ms,
+        }
+        log(f"hs 64+64: {hs_ms:.2f} ms/step")
+
+    if not args.no_cpu_baseline:
+        try:
+            result["cpu_baseline"] = cpu_baseline(cfg, ro, rv, args.cpu_rays)
+        except FileNotFoundError as e:
+            result["cpu_baseline"] = None
+            log(f"cpu baseline skipped: {e}")
+
+    print(json.dumps(result))
+
+
+if __name__ == "__main__":
+    main()

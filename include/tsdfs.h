@@ -1,0 +1,224 @@
+/*
+ * tsdfs.h - C ABI of libtsdfs.so, the MI355X (gfx950) hot path of
+ * TSDF-Sampling (Min, Cha, Won, Lim, "TSDF-Sampling: Efficient Sampling for
+ * Neural Surface Field using Truncated Signed Distance Field").
+ *
+ * Conventions for every call
+ *   - Array arguments are DEVICE pointers, allocated and owned by the caller,
+ *     contiguous, row-major.  No call allocates device memory except
+ *     tsdfs_field_create (weights).  Workspaces are caller-provided; their
+ *     sizes are returned by the *_ws_bytes queries.
+ *   - `stream` is a hipStream_t (NULL = default stream).  Every call is
+ *     asynchronous on that stream unless stated otherwise.
+ *   - Return value: TSDFS_OK (0) or a negative error code; a message for the
+ *     last error of the calling thread is returned by tsdfs_last_error().
+ *     Arguments are validated on the host before anything is launched; an
+ *     invalid call launches nothing and leaves outputs untouched.
+ *   - Discrete outputs (voxel indices, counts, statuses, offsets) and the
+ *     bound parameters t_n, t_f are deterministic and bit-identical from run
+ *     to run.
+ *
+ * Voxel traversal ("NextVoxel" is left undefined in the paper): a ray is
+ * snapped to the 2^-20 m lattice, O = rne(o 2^20), V = rne(v 2^20), and
+ * voxels are visited in the order a 6-connected walk crosses voxel faces
+ * (ties x < y < z), using exact integer arithmetic.  The parameter of a
+ * crossing is an exact rational num/den, reported as its correctly rounded
+ * FP32 value.  A ray is INVALID (status 3) when a component of o or v is
+ * not finite, when |V|^2 differs from 2^40 by more than 2^31 (v not a unit
+ * vector to ~2^-9), or when a grid face is 2^24 lattice units (16 m) or
+ * more from the origin along some axis.
+ */
+#ifndef TSDFS_H
+#define TSDFS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    TSDFS_OK = 0,
+    TSDFS_EINVAL = -1,      /* bad shape, NULL pointer, grid not on the lattice */
+    TSDFS_ECAPACITY = -2,   /* an output capacity is too small */
+    TSDFS_EHIP = -3,        /* HIP runtime error */
+    TSDFS_EUNSUPPORTED = -4 /* network shape or precision not supported */
+};
+
+/* Per-ray status written by tsdf_ray_bounds. */
+enum {
+    TSDFS_HIT = 0,     /* both bounds found */
+    TSDFS_NO_FAR = 1,  /* near bound found, far bound = original far bound */
+    TSDFS_MISS = 2,    /* no voxel of the surface group on the ray */
+    TSDFS_INVALID = 3  /* ray not usable for exact traversal (see above) */
+};
+
+/* Voxel grid (Sec. 3.2, 4.2).  Voxel (x,y,z) covers
+ * lo + h*[x,x+1) x [y,y+1) x [z,z+1); volumes are stored x-fastest,
+ * linear index x + n[0]*(y + n[1]*z).  lo, h and d_t must be multiples of
+ * 2^-20 m, h a multiple of 2^-19 m, n[a]*h < 16 m. */
+typedef struct {
+    int32_t n[3];
+    float lo[3];
+    float h;
+    float d_t;        /* truncation distance D_T */
+    float d_s;        /* surface criterion D_s (Alg. 1, phase 1) */
+    int32_t nb_radius;/* neighbourhood (2r+1)^3 of the inside test (Alg. 1, phase 2) */
+    int32_t m_consec; /* M, consecutive inside voxels that fix t_f */
+} tsdfs_grid;
+
+const char *tsdfs_last_error(void);
+
+/* ---------------------------------------------------------------------------
+ * TSDF integration (Sec. 3.2; supplementary algorithm "TSDF integration").
+ * State = per-voxel int64 sum of clamped distances s in units of 2^-32 m,
+ * followed by per-voxel uint32 update counts (unit weights: W = count).
+ * tsdfs_state_bytes: bytes of that state.  tsdf_reset: zero it (W = 0,
+ * V "unseen").
+ */
+int tsdfs_state_bytes(const tsdfs_grid *grid, size_t *bytes);
+int tsdf_reset(const tsdfs_grid *grid, void *state, void *stream);
+
+/* Fuse training rays into the state.  o, v: [n_rays,3] FP32 (v unit);
+ * depth: [n_rays] FP32 along-ray distance to the surface, p* = o + depth v
+ * (Eq. 2 depth of the trained network, or any depth map).  Each ray visits
+ * voxels from max(0, grid entry); at voxel X, s = clamp(v.(p* - c_X), -D_T,
+ * D_T) on the snapped ray, computed exactly to 2^-40 m; while s > -D_T the
+ * voxel receives s, the first voxel with s <= -D_T ends the ray.  A depth
+ * that is not finite, <= 0, < 2^-16 m or >= 2^12 m marks a free-space ray
+ * (s = +D_T until the grid exit).  Integer atomics make the result
+ * independent of ray order.  Accumulates into `state`; call repeatedly for
+ * batches.  Optional n_updates_dev: device int64 counter incremented by the
+ * number of voxel updates (NULL to skip). */
+int tsdf_integrate(const tsdfs_grid *grid, void *state, const float *o, const float *v,
+                   const float *depth, int64_t n_rays, int64_t *n_updates_dev, void *stream);
+
+/* V[N] (FP32, metres) = mean of received s, or -D_T for unseen voxels (the
+ * paper's initial "-1" in units of D_T).  flags[N] (u8): bit0 = V <= D_s,
+ * bit1 = every voxel of the (2r+1)^3 cube centred on the voxel has V < 0
+ * (voxels outside the grid count as unseen, i.e. negative).  V may be NULL. */
+int tsdf_finalize(const tsdfs_grid *grid, const void *state, float *V, uint8_t *flags,
+                  void *stream);
+
+/* ---------------------------------------------------------------------------
+ * Sample-boundary detection, Alg. 1 (Sec. 3.3).  Per ray: phase 1 walks
+ * voxels from max(0, grid entry) to the first with flag bit0; t_n = the
+ * parameter where it is entered.  Phase 2 starts at that voxel, counts
+ * consecutive voxels with bit1 and, when the count reaches M, sets t_f to the
+ * parameter where that voxel is left (status HIT).  A voxel is visited only
+ * while its entry parameter (FP32) is < t_far; if the walk ends first,
+ * t_f = min(t_far, exit of the last visited voxel) (status NO_FAR).  No
+ * phase-1 voxel: status MISS, t_n = t_f = 0, first_hit = -1, n_vox = 0.
+ * Outputs [n_rays]: t_n, t_f (FP32), first_hit (int32 linear voxel index),
+ * n_vox (voxels from first_hit to the last voxel of the bound, inclusive),
+ * status (u8); n_steps (optional, NULL to skip): voxels visited in total.
+ * t_far must be > 0 (may be +inf). */
+int tsdf_ray_bounds(const tsdfs_grid *grid, const uint8_t *flags, const float *o,
+                    const float *v, int64_t n_rays, float t_far, float *t_n, float *t_f,
+                    int32_t *first_hit, int32_t *n_vox, uint8_t *status, int32_t *n_steps,
+                    void *stream);
+
+/* Grid parameter range of each ray as FP32: t_in = max(0, entry),
+ * t_out = exit (0, 0 when the ray misses the grid or is invalid).  This is
+ * the full range that hierarchical sampling starts from. */
+int tsdf_ray_range(const tsdfs_grid *grid, const float *o, const float *v, int64_t n_rays,
+                   float *t_in, float *t_out, void *stream);
+
+/* ---------------------------------------------------------------------------
+ * Adaptive sample placement (Sec. 3.4): n_i = clamp(ceil(n_vox rho_num /
+ * rho_den), n_min, n_max) for HIT / NO_FAR rays, 0 otherwise (n_min = n_max
+ * is the fixed-count "naive" variant).  offsets [n_rays+1] = exclusive
+ * prefix sum; sample k of ray i sits at the midpoint of the k-th of n_i
+ * equal sections of [t_n, t_f]: t = t_n + (k + 1/2) dt, dt = (t_f - t_n)/n_i.
+ * Outputs t, dt (FP32), ray_id (int32) have room for s_cap samples.
+ * s_total_dev (device int64) receives the total.  If s_total_host is not
+ * NULL the call synchronises the stream, writes the total there and returns
+ * TSDFS_ECAPACITY when it exceeds s_cap; otherwise samples past s_cap are
+ * dropped and the caller checks *s_total_dev.  ws: place_samples_ws_bytes. */
+int place_samples_ws_bytes(int64_t n_rays, size_t *bytes);
+int place_samples(const float *t_n, const float *t_f, const int32_t *n_vox,
+                  const uint8_t *status, int64_t n_rays, int32_t rho_num, int32_t rho_den,
+                  int32_t n_min, int32_t n_max, int32_t *counts, int32_t *offsets, float *t,
+                  float *dt, int32_t *ray_id, int64_t s_cap, int64_t *s_total_dev,
+                  int64_t *s_total_host, void *ws, size_t ws_bytes, void *stream);
+
+/* Hierarchical-sampling baseline (the comparison sampler of Sec. 2.2 and the
+ * tables; coarse + fine by inverse transform sampling).
+ * hs_coarse: n_coarse samples per ray at the midpoints of n_coarse equal
+ * sections of [t_in, t_out]; t, ray_id: [n_rays * n_coarse].
+ * hs_upsample: from the coarse points and their SDF values f_coarse
+ * ([n_rays, 64] each), the NeuS opacity of the 63 coarse intervals,
+ * alpha_k = max((Phi(f_k) - Phi(f_{k+1})) / Phi(f_k), 0), Phi(x) =
+ * sigmoid(s x), weights w_k = T_k alpha_k, probabilities (w_k + 1e-5) /
+ * sum(w + 1e-5); 64 fine points at the quantiles u_m = (m + 1/2)/64 of that
+ * piecewise-uniform density; the 128 points sorted; samples at the midpoints
+ * of the sections [y_i, y_{i+1}] (the last ends at t_out).  Outputs t, dt,
+ * ray_id [n_rays * 128] and offsets [n_rays + 1] (ray i owns 128 i ..).
+ * Only n_coarse = n_fine = 64 is supported (TSDFS_EUNSUPPORTED otherwise). */
+int hs_coarse(const float *t_in, const float *t_out, int64_t n_rays, int32_t n_coarse, float *t,
+              int32_t *ray_id, void *stream);
+int hs_upsample(const float *t_coarse, const float *f_coarse, const float *t_out,
+                int64_t n_rays, int32_t n_coarse, int32_t n_fine, float s, float *t, float *dt,
+                int32_t *ray_id, int32_t *offsets, void *stream);
+
+/* ---------------------------------------------------------------------------
+ * Neural field (network of Sec. 3.1, Eq. 1; normal of the supplementary
+ * "Normal Estimation").  SDF network: x_hat = (p - center)/scale, positional
+ * encoding gamma (identity + sin/cos at 2^0..2^(L-1)), hidden softplus_beta
+ * layers (optional skip layer whose input is [h, gamma]/sqrt(2)), output
+ * [y0, feat]; f = scale*y0 in metres; grad f = d f/d p.  Colour network:
+ * [x_hat, v, grad f, feat] -> ReLU hidden layers -> sigmoid(3).
+ * Parameters (host FP32): per linear layer W [out][in] row-major then b.
+ * Supported shapes: width 64 or 256 (multiple of 32), <= 8 SDF hidden
+ * layers, <= 4 colour hidden layers, feat = width. */
+typedef struct {
+    int32_t width;       /* hidden width of both networks */
+    int32_t n_hidden;    /* SDF hidden layers */
+    int32_t pe_freqs;    /* L (0 = raw x_hat) */
+    int32_t skip_at;     /* index of the SDF layer with the skip input, -1 = none */
+    int32_t n_feat;      /* feature outputs (must equal width) */
+    int32_t col_hidden;  /* colour hidden layers */
+    float beta;          /* softplus sharpness */
+    float center[3];
+    float scale;
+} tsdfs_field_desc;
+
+typedef struct tsdfs_field tsdfs_field;
+
+enum { TSDFS_FP32 = 0, TSDFS_BF16 = 1 };
+
+int tsdfs_field_create(const tsdfs_field_desc *desc, const float *sdf_params_host,
+                       const float *color_params_host, tsdfs_field **out);
+int tsdfs_field_destroy(tsdfs_field *field);
+
+/* Evaluate the field at p = o[ray_id] + t v[ray_id] for min(*s_count_dev,
+ * s_cap) samples (s_count_dev may be NULL: s_cap samples).  Outputs [S]:
+ * f (metres), grad_f [S,3] and rgb [S,3]; with grad_f == rgb == NULL only f
+ * is computed (SDF forward only).  precision: TSDFS_FP32 or TSDFS_BF16
+ * (BF16 GEMM inputs, FP32 accumulation; everything else FP32).
+ * ws: sdf_mlp_fwd_ws_bytes. */
+int sdf_mlp_fwd_ws_bytes(const tsdfs_field *field, size_t *bytes);
+int sdf_mlp_fwd(const tsdfs_field *field, const float *o, const float *v, const float *t,
+                const int32_t *ray_id, int64_t s_cap, const int64_t *s_count_dev,
+                int32_t precision, float *f, float *grad_f, float *rgb, void *ws,
+                size_t ws_bytes, void *stream);
+
+/* ---------------------------------------------------------------------------
+ * Volume rendering, Eq. 1 (colour), Eq. 2 (depth) and the supplementary
+ * normal, with the NeuS discrete opacity of a section [t - dt/2, t + dt/2]:
+ * cos = min(v . grad f, 0), f_prev/next = f -/+ cos dt/2,
+ * log(1 - alpha) = logsigmoid(s f_next) - logsigmoid(s f_prev),
+ * T_i = exp(sum_{j<i} log(1 - alpha_j)), w_i = T_i alpha_i.
+ * Per ray i (samples offsets[i]..offsets[i+1]-1): rgb = sum w c,
+ * depth = sum w t / sum w, normal = sum w n_hat / sum w (0 when sum w = 0),
+ * acc = sum w.  v: [n_rays,3]; w (optional, [S]).  s = NeuS sharpness. */
+int composite(const int32_t *offsets, int64_t n_rays, const float *v, const float *t,
+              const float *dt, const float *f, const float *grad_f, const float *rgb,
+              float s, float *out_rgb, float *out_depth, float *out_normal, float *out_acc,
+              float *w, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TSDFS_H */

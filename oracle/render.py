@@ -92,23 +92,31 @@ def hs_coarse(t_in, t_out, n_coarse):
     return t0 + (k + 0.5) * (t1 - t0) / n_coarse
 
 
-def hs_upsample(z, f, s, n_fine):
-    """Fine samples by inverse transform of the coarse weight distribution.
+def hs_cdf(z, f, s):
+    """Knots of the coarse-weight CDF: value at z_k is sum_{j<k} pdf_j.
 
     Interval k = [z_k, z_{k+1}] gets alpha_k = max((Phi(f_k) - Phi(f_{k+1})) /
     Phi(f_k), 0) from the SDF at its two ends, w_k = T_k alpha_k, and
-    probability (w_k + 1e-5) / sum_j (w_j + 1e-5).  The fine samples are the
-    quantiles u_m = (m + 1/2) / n_fine of that piecewise-uniform density.
+    probability (w_k + 1e-5) / sum_j (w_j + 1e-5).
     """
-    z = np.asarray(z, np.float64)
     f = np.asarray(f, np.float64)
-    R, n = z.shape
+    R, n = f.shape
     phi = 1.0 / (1.0 + np.exp(-s * f))
     alpha = np.clip((phi[:, :-1] - phi[:, 1:]) / phi[:, :-1], 0.0, 1.0)
     T = np.cumprod(np.concatenate([np.ones((R, 1)), 1.0 - alpha[:, :-1]], axis=1), axis=1)
     w = T * alpha + 1e-5
     pdf = w / w.sum(1, keepdims=True)
     cdf = np.concatenate([np.zeros((R, 1)), np.cumsum(pdf, axis=1)], axis=1)  # [R, n]
+    return pdf, cdf
+
+
+def hs_upsample(z, f, s, n_fine):
+    """Fine samples by inverse transform of the coarse weight distribution:
+    the quantiles u_m = (m + 1/2) / n_fine of the piecewise-uniform density
+    of hs_cdf."""
+    z = np.asarray(z, np.float64)
+    R, n = z.shape
+    pdf, cdf = hs_cdf(z, f, s)
     u = (np.arange(n_fine) + 0.5) / n_fine
     fine = np.zeros((R, n_fine))
     for r in range(R):

@@ -1,0 +1,221 @@
+"""Thin torch-facing wrappers over the C ABI (argument marshalling only).
+
+Every function takes device tensors, allocates outputs with torch (device
+memory and the current stream are all torch provides) and calls one entry
+point of libtsdfs.so; all arithmetic runs in the HIP kernels.
+"""
+from __future__ import annotations
+
+import ctypes
+
+import torch
+
+from . import _lib as L
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _p(t):
+    if t is None:
+        return None
+    assert t.is_cuda and t.is_contiguous(), "expected a contiguous device tensor"
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _dev():
+    return torch.device("cuda", torch.cuda.current_device())
+
+
+def make_grid(n, lo, h, d_t, d_s, nb_radius=2, m_consec=15):
+    g = L.Grid()
+    g.n[:] = [int(x) for x in n]
+    g.lo[:] = [float(x) for x in lo]
+    g.h, g.d_t, g.d_s = float(h), float(d_t), float(d_s)
+    g.nb_radius, g.m_consec = int(nb_radius), int(m_consec)
+    return g
+
+
+def n_voxels(g):
+    return int(g.n[0]) * int(g.n[1]) * int(g.n[2])
+
+
+def state_bytes(g):
+    b = ctypes.c_size_t(0)
+    L.check(L.load().tsdfs_state_bytes(ctypes.byref(g), ctypes.byref(b)))
+    return b.value
+
+
+def new_state(g):
+    st = torch.empty(state_bytes(g), dtype=torch.uint8, device=_dev())
+    L.check(L.load().tsdf_reset(ctypes.byref(g), _p(st), _stream()))
+    return st
+
+
+def state_views(g, st):
+    """(sum [N] int64 in 2^-32 m, count [N] int32-as-uint32) views of a state."""
+    N = n_voxels(g)
+    s = st[: 8 * N].view(torch.int64)
+    c = st[8 * N: 12 * N].view(torch.int32)
+    return s, c
+
+
+def integrate(g, st, o, v, depth, n_updates=None):
+    L.check(L.load().tsdf_integrate(ctypes.byref(g), _p(st), _p(o), _p(v), _p(depth), o.shape[0],
+                                    _p(n_updates), _stream()))
+
+
+def finalize(g, st, want_v=True):
+    N = n_voxels(g)
+    V = torch.empty(N, dtype=torch.float32, device=_dev()) if want_v else None
+    fl = torch.empty(N, dtype=torch.uint8, device=_dev())
+    L.check(L.load().tsdf_finalize(ctypes.byref(g), _p(st), _p(V), _p(fl), _stream()))
+    return V, fl
+
+
+def ray_bounds(g, flags, o, v, t_far=float("inf"), steps=False):
+    R = o.shape[0]
+    d = _dev()
+    out = dict(t_n=torch.empty(R, dtype=torch.float32, device=d),
+               t_f=torch.empty(R, dtype=torch.float32, device=d),
+               first_hit=torch.empty(R, dtype=torch.int32, device=d),
+               n_vox=torch.empty(R, dtype=torch.int32, device=d),
+               status=torch.empty(R, dtype=torch.uint8, device=d))
+    out["n_steps"] = torch.empty(R, dtype=torch.int32, device=d) if steps else None
+    L.check(L.load().tsdf_ray_bounds(ctypes.byref(g), _p(flags), _p(o), _p(v), R, float(t_far),
+                                     _p(out["t_n"]), _p(out["t_f"]), _p(out["first_hit"]),
+                                     _p(out["n_vox"]), _p(out["status"]), _p(out["n_steps"]),
+                                     _stream()))
+    return out
+
+
+def ray_range(g, o, v):
+    R = o.shape[0]
+    t_in = torch.empty(R, dtype=torch.float32, device=_dev())
+    t_out = torch.empty(R, dtype=torch.float32, device=_dev())
+    L.check(L.load().tsdf_ray_range(ctypes.byref(g), _p(o), _p(v), R, _p(t_in), _p(t_out),
+                                    _stream()))
+    return t_in, t_out
+
+
+def place_ws_bytes(n_rays):
+    b = ctypes.c_size_t(0)
+    L.check(L.load().place_samples_ws_bytes(n_rays, ctypes.byref(b)))
+    return b.value
+
+
+def place(bounds, rho_num, rho_den, n_min, n_max, s_cap=None, sync=True, ws=None):
+    """Adaptive placement.  With sync=True the total is read back and the
+    sample arrays are trimmed to it; otherwise arrays of s_cap are returned
+    together with the device total."""
+    R = bounds["t_n"].shape[0]
+    d = _dev()
+    if s_cap is None:
+        s_cap = R * n_max
+    counts = torch.empty(R, dtype=torch.int32, device=d)
+    offsets = torch.empty(R + 1, dtype=torch.int32, device=d)
+    t = torch.empty(max(s_cap, 1), dtype=torch.float32, device=d)
+    dt = torch.empty(max(s_cap, 1), dtype=torch.float32, device=d)
+    ray_id = torch.empty(max(s_cap, 1), dtype=torch.int32, device=d)
+    s_total = torch.zeros(1, dtype=torch.int64, device=d)
+    if ws is None:
+        ws = torch.empty(max(place_ws_bytes(R), 8), dtype=torch.uint8, device=d)
+    host_total = ctypes.c_int64(-1)
+    L.check(L.load().place_samples(_p(bounds["t_n"]), _p(bounds["t_f"]), _p(bounds["n_vox"]),
+                                   _p(bounds["status"]), R, rho_num, rho_den, n_min, n_max,
+                                   _p(counts), _p(offsets), _p(t), _p(dt), _p(ray_id), s_cap,
+                                   _p(s_total), ctypes.byref(host_total) if sync else None,
+                                   _p(ws), ws.numel(), _stream()))
+    out = dict(counts=counts, offsets=offsets, t=t, dt=dt, ray_id=ray_id, s_total=s_total)
+    if sync:
+        S = host_total.value
+        out.update(t=t[:S], dt=dt[:S], ray_id=ray_id[:S], S=S)
+    return out
+
+
+def hs_coarse(t_in, t_out, n_coarse=64):
+    R = t_in.shape[0]
+    t = torch.empty(R * n_coarse, dtype=torch.float32, device=_dev())
+    rid = torch.empty(R * n_coarse, dtype=torch.int32, device=_dev())
+    L.check(L.load().hs_coarse(_p(t_in), _p(t_out), R, n_coarse, _p(t), _p(rid), _stream()))
+    return t, rid
+
+
+def hs_upsample(t_coarse, f_coarse, t_out, s, n_coarse=64, n_fine=64):
+    R = t_out.shape[0]
+    n = R * (n_coarse + n_fine)
+    d = _dev()
+    t = torch.empty(n, dtype=torch.float32, device=d)
+    dt = torch.empty(n, dtype=torch.float32, device=d)
+    rid = torch.empty(n, dtype=torch.int32, device=d)
+    off = torch.empty(R + 1, dtype=torch.int32, device=d)
+    L.check(L.load().hs_upsample(_p(t_coarse), _p(f_coarse), _p(t_out), R, n_coarse, n_fine,
+                                 float(s), _p(t), _p(dt), _p(rid), _p(off), _stream()))
+    return dict(t=t, dt=dt, ray_id=rid, offsets=off)
+
+
+class Field:
+    """Device copy of the SDF + colour networks (packed for MFMA)."""
+
+    def __init__(self, width, n_hidden, pe_freqs, skip_at, n_feat, col_hidden, beta, center,
+                 scale, sdf_params, color_params):
+        import numpy as np
+        d = L.FieldDesc()
+        d.width, d.n_hidden, d.pe_freqs, d.skip_at = width, n_hidden, pe_freqs, skip_at
+        d.n_feat, d.col_hidden, d.beta = n_feat, col_hidden, float(beta)
+        d.center[:] = [float(x) for x in center]
+        d.scale = float(scale)
+        self._sp = np.ascontiguousarray(sdf_params, dtype=np.float32)
+        self._cp = np.ascontiguousarray(color_params, dtype=np.float32)
+        h = ctypes.c_void_p(None)
+        L.check(L.load().tsdfs_field_create(ctypes.byref(d), self._sp.ctypes.data_as(ctypes.c_void_p),
+                                            self._cp.ctypes.data_as(ctypes.c_void_p),
+                                            ctypes.byref(h)))
+        self.handle = h
+        b = ctypes.c_size_t(0)
+        L.check(L.load().sdf_mlp_fwd_ws_bytes(self.handle, ctypes.byref(b)))
+        self.ws_bytes = b.value
+        self._ws = None
+
+    def workspace(self):
+        if self._ws is None:
+            self._ws = torch.empty(self.ws_bytes, dtype=torch.uint8, device=_dev())
+        return self._ws
+
+    def forward(self, o, v, t, ray_id, s_count=None, precision=L.FP32, full=True, s_cap=None):
+        S = t.shape[0] if s_cap is None else s_cap
+        d = _dev()
+        f = torch.empty(max(S, 1), dtype=torch.float32, device=d)
+        g = torch.empty((max(S, 1), 3), dtype=torch.float32, device=d) if full else None
+        rgb = torch.empty((max(S, 1), 3), dtype=torch.float32, device=d) if full else None
+        ws = self.workspace()
+        L.check(L.load().sdf_mlp_fwd(self.handle, _p(o), _p(v), _p(t), _p(ray_id), S, _p(s_count),
+                                     precision, _p(f), _p(g), _p(rgb), _p(ws), ws.numel(),
+                                     _stream()))
+        return f[:S], (g[:S] if full else None), (rgb[:S] if full else None)
+
+    def close(self):
+        if self.handle:
+            L.load().tsdfs_field_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def composite(offsets, v, t, dt, f, grad, rgb, s, want_w=False):
+    R = offsets.shape[0] - 1
+    d = _dev()
+    out = dict(rgb=torch.empty((R, 3), dtype=torch.float32, device=d),
+               depth=torch.empty(R, dtype=torch.float32, device=d),
+               normal=torch.empty((R, 3), dtype=torch.float32, device=d),
+               acc=torch.empty(R, dtype=torch.float32, device=d))
+    out["w"] = torch.empty(max(t.shape[0], 1), dtype=torch.float32, device=d) if want_w else None
+    L.check(L.load().composite(_p(offsets), R, _p(v), _p(t), _p(dt), _p(f), _p(grad), _p(rgb),
+                               float(s), _p(out["rgb"]), _p(out["depth"]), _p(out["normal"]),
+                               _p(out["acc"]), _p(out["w"]), _stream()))
+    return out

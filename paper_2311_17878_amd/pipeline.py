@@ -1,0 +1,104 @@
+"""The TSDF-Sampling render path and the hierarchical baseline, as sequences
+of C-ABI calls on torch's current stream.
+
+Render (Sec. 3.3-3.4 + Eq. 1/2): Alg. 1 bounds -> adaptive placement ->
+field (SDF, grad f, colour) -> compositing.  The placement total stays on the
+device (no host synchronisation inside a frame): the field reads the sample
+count from device memory and the compositing reads the ray offsets.
+"""
+from __future__ import annotations
+
+import torch
+
+from . import ops
+from ._lib import FP32
+
+
+class _Marks:
+    """Records consecutive (start, end) event pairs per stage name."""
+
+    def __init__(self, events):
+        self.events = events
+        self.cur = None
+
+    def __call__(self, name):
+        if self.events is None:
+            return
+        e = torch.cuda.Event(enable_timing=True)
+        e.record()
+        if self.cur is not None:
+            self.events.setdefault(self.cur[0], []).append((self.cur[1], e))
+        self.cur = (name, e) if name is not None else None
+
+
+class TsdfRenderer:
+    def __init__(self, grid, field, rho_num, rho_den, n_min, n_max, s, t_far=float("inf"),
+                 precision=FP32):
+        self.grid = grid
+        self.field = field
+        self.rho = (int(rho_num), int(rho_den))
+        self.n_min, self.n_max = int(n_min), int(n_max)
+        self.s = float(s)
+        self.t_far = float(t_far)
+        self.precision = precision
+        self.state = None
+        self.V = None
+        self.flags = None
+
+    # ---------------------------------------------------------- volume ----
+    def integrate(self, o, v, depth, batch=1 << 22, n_updates=None):
+        """Fuse training rays (device tensors) into the TSDF state."""
+        if self.state is None:
+            self.state = ops.new_state(self.grid)
+        R = o.shape[0]
+        for s in range(0, R, batch):
+            e = min(R, s + batch)
+            ops.integrate(self.grid, self.state, o[s:e], v[s:e], depth[s:e], n_updates)
+        return self.state
+
+    def finalize(self, want_v=True):
+        self.V, self.flags = ops.finalize(self.grid, self.state, want_v)
+        return self.V, self.flags
+
+    # ---------------------------------------------------------- render ----
+    def render(self, o, v, sync=False, keep=False, events=None):
+        """Render rays o, v [R,3].  `events`: optional dict that receives
+        (start, end) torch.cuda.Event pairs per stage, recorded on the
+        stream the kernels run on."""
+        mark = _Marks(events)
+        mark("bounds")
+        b = ops.ray_bounds(self.grid, self.flags, o, v, self.t_far)
+        mark("place")
+        R = o.shape[0]
+        p = ops.place(b, self.rho[0], self.rho[1], self.n_min, self.n_max, s_cap=R * self.n_max,
+                      sync=sync)
+        s_count = None if sync else p["s_total"]
+        mark("field")
+        f, g, rgb = self.field.forward(o, v, p["t"], p["ray_id"], s_count=s_count,
+                                       precision=self.precision, s_cap=p["t"].shape[0])
+        mark("composite")
+        out = ops.composite(p["offsets"], v, p["t"], p["dt"], f, g, rgb, self.s)
+        mark(None)
+        if keep:
+            out.update(bounds=b, place=p, f=f, grad=g, rgb_s=rgb)
+        out["s_total"] = p["s_total"]
+        return out
+
+    def render_hs(self, o, v, keep=False, events=None):
+        mark = _Marks(events)
+        mark("range+coarse")
+        t_in, t_out = ops.ray_range(self.grid, o, v)
+        tc, rid = ops.hs_coarse(t_in, t_out, 64)
+        mark("field_coarse")
+        fc, _, _ = self.field.forward(o, v, tc, rid, precision=self.precision, full=False)
+        mark("upsample")
+        up = ops.hs_upsample(tc, fc, t_out, self.s)
+        mark("field")
+        f, g, rgb = self.field.forward(o, v, up["t"], up["ray_id"], precision=self.precision)
+        mark("composite")
+        out = ops.composite(up["offsets"], v, up["t"], up["dt"], f, g, rgb, self.s)
+        mark(None)
+        if keep:
+            out.update(t_in=t_in, t_out=t_out, t_coarse=tc, f_coarse=fc, up=up, f=f, grad=g,
+                       rgb_s=rgb)
+        return out
