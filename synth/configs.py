@@ -244,7 +244,7 @@ def _c2():
         grid=Grid((256, 256, 256), (-0.5, -0.5, -0.5), h, 5 * h, h),
         sdf=SdfNet(), color=ColorNet(),
         in_center=(3.0, 3.0, 1.5), in_scale=3.0,
-        sampling=Sampling(1, 1, 1, 64),
+        sampling=Sampling(1, 2, 1, 64),
         build_scene=_scene_c2,
         integ_views=_room_views(0, 100, size, 384, 384, 90.0),
         render_view=render,
@@ -266,7 +266,7 @@ def _c5():
         grid=Grid((512, 512, 512), (-0.5, -0.5, -0.5), h, 5 * h, h),
         sdf=SdfNet(), color=ColorNet(),
         in_center=(6.0, 4.0, 1.5), in_scale=6.0,
-        sampling=Sampling(1, 1, 1, 64),
+        sampling=Sampling(1, 2, 1, 64),
         precision="bf16",
         build_scene=_scene_c5,
         integ_views=_room_views(0, 300, size, 512, 512, 90.0),
