@@ -17,73 +17,9 @@
 #include <string.h>
 #include <vector>
 
-#include "common.hpp"
+#include "field_common.hpp"
 
 namespace tsdfs {
-
-typedef float floatx16 __attribute__((ext_vector_type(16)));
-
-constexpr int kTile = 128;     // samples per workgroup tile
-constexpr int kWaves = 8;      // one 32-row output tile per wave (<= 256 outputs)
-constexpr int kThreads = kWaves * 64;
-constexpr int kParts = kThreads / kTile;  // partial sums per sample in dot products
-constexpr int kMaxRows = 272;  // LDS activation rows (colour input 9 + 256 -> 272)
-constexpr int kMaxHidden = 8;
-constexpr int kMaxColor = 4;
-constexpr int kScratchLayer = 8 * 4 * 16 * 64;  // floats per layer per workgroup
-
-struct Layer {
-    const float *Wp;   // packed A operand [n_tiles][K8/8][64][4]
-    const float *b;    // bias [n_tiles*32] (zero padded), may be NULL
-    int K8;            // K padded to a multiple of 8
-    int n_tiles;       // ceil(n_out / 32)
-    int n_out;
-};
-
-struct Plan {
-    int n_hidden, skip_at, d_gamma, pe, width, n_feat, col_hidden;
-    float beta, inv_beta, scale;
-    float center[3];
-    Layer fwd[kMaxHidden];
-    Layer feat;
-    Layer bwd[kMaxHidden];
-    Layer col[kMaxColor];
-    const float *wf;    // f row of the output layer [width]
-    float bf;
-    const float *wrgb;  // [3][width]
-    float brgb[3];
-};
-
-}  // namespace tsdfs
-
-struct tsdfs_field {
-    tsdfs_field_desc desc;
-    tsdfs::Plan plan;
-    float *dev = nullptr;   // all packed weights
-    int n_wg = 0;           // persistent grid size
-};
-
-namespace tsdfs {
-
-// ---------------------------------------------------------------- device ----
-
-__device__ __forceinline__ float gamma_value(const float *xh, int j) {
-    // [x_hat, sin(2^k x_hat), cos(2^k x_hat)], k = 0..L-1, each over (x, y, z)
-    if (j < 3) return xh[j * kTile];
-    int jj = j - 3, k = jj / 6, rem = jj % 6, a = rem % 3;
-    float x = ldexpf(xh[a * kTile], k);
-    return rem < 3 ? sinf(x) : cosf(x);
-}
-
-// d gamma_j / d x_hat_a (only one component a is non-zero); returns a.
-__device__ __forceinline__ int gamma_deriv(const float *xh, int j, float &d) {
-    if (j < 3) { d = 1.0f; return j; }
-    int jj = j - 3, k = jj / 6, rem = jj % 6, a = rem % 3;
-    float sc = ldexpf(1.0f, k);
-    float x = sc * xh[a * kTile];
-    d = rem < 3 ? sc * cosf(x) : -sc * sinf(x);
-    return a;
-}
 
 // acc[c] = sum_k A[t*32 + row][k] * act[k][c*32 + col], t = this wave's tile.
 __device__ __forceinline__ void gemm_fp32(const Layer &L, const float *act, floatx16 (&acc)[4],
@@ -436,6 +372,32 @@ static void pack_a(std::vector<float> &out, const float *M, int n_out, int K, in
                 }
 }
 
+static uint16_t to_bf16(float x) {
+    uint32_t u;
+    memcpy(&u, &x, 4);
+    if ((u & 0x7f800000u) == 0x7f800000u) return (uint16_t)(u >> 16);  // inf / nan
+    u += 0x7fffu + ((u >> 16) & 1u);                                      // round to nearest even
+    return (uint16_t)(u >> 16);
+}
+
+// Pack M as the A operand of v_mfma_f32_32x32x16_bf16:
+// P[((t*K16 + kk)*64 + lane)*8 + j] = bf16(M[t*32 + lane%32][16 kk + 8 (lane/32) + j]).
+static void pack_a_bf16(std::vector<uint16_t> &out, const float *M, int n_out, int K, int ld,
+                        bool transpose) {
+    int K16 = (K + 15) / 16, nt = (n_out + 31) / 32;
+    size_t base = out.size();
+    out.resize(base + (size_t)nt * K16 * 64 * 8, 0);
+    for (int t = 0; t < nt; ++t)
+        for (int kk = 0; kk < K16; ++kk)
+            for (int lane = 0; lane < 64; ++lane)
+                for (int j = 0; j < 8; ++j) {
+                    int r = t * 32 + (lane & 31), k = 16 * kk + 8 * (lane >> 5) + j;
+                    if (r < n_out && k < K)
+                        out[base + ((size_t)(t * K16 + kk) * 64 + lane) * 8 + j] =
+                            to_bf16(transpose ? M[(size_t)k * ld + r] : M[(size_t)r * ld + k]);
+                }
+}
+
 static void pack_bias(std::vector<float> &out, const float *b, int n_out) {
     int nt = (n_out + 31) / 32;
     size_t base = out.size();
@@ -489,20 +451,24 @@ int tsdfs_field_create(const tsdfs_field_desc *d, const float *sdf_params,
     P.scale = d->scale;
     for (int a = 0; a < 3; ++a) P.center[a] = d->center[a];
 
-    // offsets into the packed host buffer, resolved to device pointers below
+    // offsets into the packed host buffers, resolved to device pointers below
     std::vector<float> buf;
-    struct Ref { Layer *L; size_t w, b; bool has_b; };
+    std::vector<uint16_t> bbuf;
+    struct Ref { Layer *L; size_t w, wb, b; bool has_b; };
     std::vector<Ref> refs;
     auto add_layer = [&](Layer *L, const float *M, int n_out, int K, int ld, bool tr,
                          const float *bias) {
         L->K8 = round8(K);
+        L->K16 = (K + 15) / 16;
         L->n_tiles = (n_out + 31) / 32;
         L->n_out = n_out;
         size_t w = buf.size();
         pack_a(buf, M, n_out, K, ld, tr);
+        size_t wb = bbuf.size();
+        pack_a_bf16(bbuf, M, n_out, K, ld, tr);
         size_t b = buf.size();
         if (bias) pack_bias(buf, bias, n_out);
-        refs.push_back({L, w, b, bias != nullptr});
+        refs.push_back({L, w, wb, b, bias != nullptr});
     };
     // SDF parameters: per layer W [out][in] then b
     const float *p = sdf_params;
@@ -534,21 +500,29 @@ int tsdfs_field_create(const tsdfs_field_desc *d, const float *sdf_params,
     while (buf.size() % 4) buf.push_back(0.0f);
     for (int j = 0; j < 3; ++j) P.brgb[j] = q[(size_t)3 * W + j];
 
-    hipError_t e = hipMalloc((void **)&F->dev, buf.size() * sizeof(float));
-    if (e != hipSuccess) {
-        delete F;
-        set_error("hipMalloc failed: %s", hipGetErrorString(e));
-        return TSDFS_EHIP;
-    }
-    e = hipMemcpy(F->dev, buf.data(), buf.size() * sizeof(float), hipMemcpyHostToDevice);
-    if (e != hipSuccess) {
+    size_t fbytes = buf.size() * sizeof(float);
+    size_t bbytes = (bbuf.size() * sizeof(uint16_t) + 255) / 256 * 256;
+    hipError_t e = hipMalloc((void **)&F->dev, fbytes + bbytes);
+    if (e == hipSuccess) e = hipMemcpy(F->dev, buf.data(), fbytes, hipMemcpyHostToDevice);
+    uint16_t *devb = (uint16_t *)((char *)F->dev + (fbytes + 255) / 256 * 256);
+    if (e == hipSuccess && fbytes % 256 != 0) {
+        // keep the BF16 block 256-byte aligned inside the single allocation
         (void)hipFree(F->dev);
+        e = hipMalloc((void **)&F->dev, (fbytes + 255) / 256 * 256 + bbytes);
+        if (e == hipSuccess) e = hipMemcpy(F->dev, buf.data(), fbytes, hipMemcpyHostToDevice);
+        devb = (uint16_t *)((char *)F->dev + (fbytes + 255) / 256 * 256);
+    }
+    if (e == hipSuccess)
+        e = hipMemcpy(devb, bbuf.data(), bbuf.size() * sizeof(uint16_t), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        if (F->dev) (void)hipFree(F->dev);
         delete F;
-        set_error("hipMemcpy failed: %s", hipGetErrorString(e));
+        set_error("device allocation / copy failed: %s", hipGetErrorString(e));
         return TSDFS_EHIP;
     }
     for (auto &r : refs) {
         r.L->Wp = F->dev + r.w;
+        r.L->Wb = (const bf16x8 *)(devb + r.wb);
         r.L->b = r.has_b ? F->dev + r.b : nullptr;
     }
     P.wf = F->dev + wf_off;
@@ -570,7 +544,8 @@ int tsdfs_field_destroy(tsdfs_field *F) {
 
 int sdf_mlp_fwd_ws_bytes(const tsdfs_field *F, size_t *bytes) {
     TSDFS_CHECK_ARG(F && bytes, "NULL argument");
-    *bytes = (size_t)F->n_wg * (F->plan.n_hidden + 1) * kScratchLayer * sizeof(float);
+    // one slot per resident workgroup: n_wg for FP32, 2 n_wg for BF16
+    *bytes = (size_t)2 * F->n_wg * (F->plan.n_hidden + 1) * kScratchLayer * sizeof(float);
     return TSDFS_OK;
 }
 
@@ -581,7 +556,7 @@ int sdf_mlp_fwd(const tsdfs_field *F, const float *o, const float *v, const floa
     TSDFS_CHECK_ARG(F != nullptr, "field is NULL");
     TSDFS_CHECK_ARG(s_cap >= 0, "s_cap must be >= 0");
     TSDFS_CHECK_ARG((grad_f == nullptr) == (rgb == nullptr), "grad_f and rgb must both be set or both NULL");
-    if (precision != TSDFS_FP32) {
+    if (precision != TSDFS_FP32 && precision != TSDFS_BF16) {
         set_error("precision %d not supported", precision);
         return TSDFS_EUNSUPPORTED;
     }
@@ -591,9 +566,16 @@ int sdf_mlp_fwd(const tsdfs_field *F, const float *o, const float *v, const floa
     sdf_mlp_fwd_ws_bytes(F, &need);
     TSDFS_CHECK_ARG(ws && ws_bytes >= need, "workspace too small (%zu < %zu)", ws_bytes, need);
     int64_t tiles = (s_cap + kTile - 1) / kTile;
-    int grid = (int)(tiles < F->n_wg ? tiles : F->n_wg);
-    hipLaunchKernelGGL(k_field_fp32, dim3(grid), dim3(kThreads), 0, as_stream(stream), F->plan, o,
-                       v, t, ray_id, s_cap, s_count_dev, f, grad_f, rgb, (float *)ws);
+    if (precision == TSDFS_BF16) {
+        int grid = (int)(tiles < 2 * F->n_wg ? tiles : 2 * F->n_wg);
+        launch_field_bf16(F->plan, grid, o, v, t, ray_id, s_cap, s_count_dev, f, grad_f, rgb,
+                          (float *)ws, as_stream(stream));
+    } else {
+        int grid = (int)(tiles < F->n_wg ? tiles : F->n_wg);
+        hipLaunchKernelGGL(k_field_fp32, dim3(grid), dim3(kThreads), 0, as_stream(stream),
+                           F->plan, o, v, t, ray_id, s_cap, s_count_dev, f, grad_f, rgb,
+                           (float *)ws);
+    }
     TSDFS_LAUNCH_CHECK();
     return TSDFS_OK;
 }

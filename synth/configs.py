@@ -242,8 +242,11 @@ def _c2():
     return Config(
         name="c2",
         grid=Grid((256, 256, 256), (-0.5, -0.5, -0.5), h, 5 * h, h),
-        sdf=SdfNet(), color=ColorNet(),
-        in_center=(3.0, 3.0, 1.5), in_scale=3.0,
+        sdf=SdfNet(inside_out=True), color=ColorNet(),
+        # inside-out geometric-init sphere of radius 1 m centred at the render
+        # camera, so that the untrained network's zero level set crosses most
+        # TSDF bounds of the view (about 2/3 of them contain t = 1 m)
+        in_center=(4.77, 2.51, 1.57), in_scale=2.0,
         sampling=Sampling(1, 2, 1, 64),
         build_scene=_scene_c2,
         integ_views=_room_views(0, 100, size, 384, 384, 90.0),

@@ -9,7 +9,8 @@ coordinates):
   * hidden layers: ``W ~ N(0, sqrt(2)/sqrt(out))``, ``b = 0``;
   * layer 0 with positional encoding: columns of the sin/cos features are 0;
   * the skip layer: columns that receive the re-injected encoding are 0;
-  * output layer: ``W ~ N(sqrt(pi)/sqrt(in), 1e-4)``, ``b = -sphere_r``.
+  * output layer: ``W ~ N(sqrt(pi)/sqrt(in), 1e-4)``, ``b = -sphere_r``
+    (both negated for an inside-out sphere, as used for indoor scenes).
 Colour network: ``W, b ~ U(-1/sqrt(in), 1/sqrt(in))``.
 """
 from __future__ import annotations
@@ -27,6 +28,7 @@ class SdfNet:
     n_feat: int = 256         # feature outputs besides f
     beta: float = 100.0       # softplus sharpness
     sphere_r: float = 0.5
+    inside_out: bool = False  # SDF ~ r - |x_hat| (the scene surrounds the sphere's centre)
 
     @property
     def d_in(self):
@@ -76,6 +78,8 @@ def sdf_params(net: SdfNet, seed: int = 42) -> np.ndarray:
         if last:
             W = rng.normal(np.sqrt(np.pi) / np.sqrt(d_in), 1e-4, size=(d_out, d_in))
             b = np.full(d_out, -net.sphere_r)
+            if net.inside_out:
+                W, b = -W, -b
         else:
             W = rng.normal(0.0, np.sqrt(2.0) / np.sqrt(d_out), size=(d_out, d_in))
             b = np.zeros(d_out)

@@ -277,3 +277,26 @@ def test_edge_cases_and_errors(c1):
     # bad t_far
     with pytest.raises(L.TsdfsError):
         ops.ray_bounds(grid, fl, dev(o), dev(v), t_far=0.0)
+
+
+def test_field_bf16_error_statement(c1):
+    """BF16 GEMM inputs (FP32 accumulation): errors against the FP64 oracle
+    are stated, and bounded by what BF16 rounding of the layer inputs allows."""
+    from paper_2311_17878_amd import _lib as L
+    cfg = c1["cfg"]
+    ro, rv = c1["render"]
+    p = c1["p"]
+    t32 = p["t"].astype(np.float32)
+    rid = p["ray_id"].astype(np.int32)
+    F = make_field(cfg)
+    f, g, rgb = F.forward(dev(ro), dev(rv), dev(t32), dev(rid), precision=L.BF16)
+    torch.cuda.synchronize()
+    of, og, orgb = OF.eval_samples(cfg, cfg.sdf_params(), cfg.color_params(), ro, rv, t32, rid)
+    ef = np.abs(host(f) - of)
+    eg = np.linalg.norm(host(g) - og, axis=1) / np.maximum(np.linalg.norm(og, axis=1), 1e-6)
+    ec = np.abs(host(rgb) - orgb)
+    print("BF16 C1: f abs err max %.3g mean %.3g | grad rel err max %.3g mean %.3g | rgb max %.3g"
+          % (ef.max(), ef.mean(), eg.max(), eg.mean(), ec.max()))
+    assert ef.max() <= 2e-2 and eg.mean() <= 2e-2 and ec.max() <= 2e-2
+    f2, _, _ = F.forward(dev(ro), dev(rv), dev(t32), dev(rid), precision=L.BF16, full=False)
+    assert torch.equal(f2, f)

@@ -152,3 +152,36 @@ def test_hierarchical_on_sampled_rays(c2):
         e = np.abs(host(out[k])[rays] - ref[k]).max()
         print("hs", k, e)
         assert e <= tol, k
+
+
+def test_bf16_field_and_image(c2):
+    """BF16 field at the full size: error against the FP64 oracle on 2048
+    seeded samples, and PSNR of the BF16 image against the FP32 image."""
+    from paper_2311_17878_amd import _lib as L
+    cfg, op = c2["cfg"], c2["op"]
+    ro, rv = c2["render"]
+    t32 = op["t"].astype(np.float32)
+    rid = op["ray_id"].astype(np.int32)
+    f, g, rgb = c2["R"].field.forward(c2["ro_d"], c2["rv_d"], dev(t32), dev(rid), precision=L.BF16)
+    torch.cuda.synchronize()
+    pick = np.sort(np.random.default_rng(0).choice(t32.size, 2048, replace=False))
+    of, og, orgb = OF.eval_samples(cfg, cfg.sdf_params(), cfg.color_params(), ro, rv, t32[pick], rid[pick])
+    ef = np.abs(host(f)[pick] - of)
+    eg = np.linalg.norm(host(g)[pick] - og, axis=1) / np.maximum(np.linalg.norm(og, axis=1), 1e-6)
+    ec = np.abs(host(rgb)[pick] - orgb)
+    print("BF16 C2: f abs err max %.3g mean %.3g | grad rel err max %.3g mean %.3g | rgb max %.3g mean %.3g"
+          % (ef.max(), ef.mean(), eg.max(), eg.mean(), ec.max(), ec.mean()))
+    assert ef.max() <= 5e-2 and eg.mean() <= 5e-2 and ec.max() <= 5e-2
+    R = c2["R"]
+    img32 = R.render(c2["ro_d"], c2["rv_d"])
+    R.precision = L.BF16
+    try:
+        img16 = R.render(c2["ro_d"], c2["rv_d"])
+    finally:
+        R.precision = L.FP32
+    mse = float(((img16["rgb"] - img32["rgb"]) ** 2).mean())
+    psnr = 10 * np.log10(1.0 / max(mse, 1e-30))
+    dd = (img16["depth"] - img32["depth"]).abs()
+    print("BF16 vs FP32 image: PSNR %.2f dB, depth abs diff mean %.3g max %.3g m" %
+          (psnr, float(dd.mean()), float(dd.max())))
+    assert psnr >= 30.0

@@ -76,10 +76,11 @@ def test_geometric_init_is_close_to_a_sphere(name):
     p = np.asarray(cfg.in_center) + cfg.in_scale * xh
     f = F.sdf_only(cfg, cfg.sdf_params(), p) / cfg.in_scale
     r = np.linalg.norm(xh, axis=1)
-    err = f - (r - cfg.sdf.sphere_r)
+    sign = -1.0 if cfg.sdf.inside_out else 1.0
+    err = f - sign * (r - cfg.sdf.sphere_r)
     # finite-width networks only approximate the sphere: loose statement
     assert np.abs(err).mean() < (0.1 if cfg.sdf.width >= 256 else 0.25)
-    assert np.corrcoef(f, r)[0, 1] > (0.9 if cfg.sdf.width >= 256 else 0.5)
+    assert sign * np.corrcoef(f, r)[0, 1] > (0.9 if cfg.sdf.width >= 256 else 0.5)
 
 
 def _plane_rays(s, n_sec, t0, t1, cos=-1.0, f0=0.7):
