@@ -218,6 +218,42 @@ int composite(const int32_t *offsets, int64_t n_rays, const float *v, const floa
               float s, float *out_rgb, float *out_depth, float *out_normal, float *out_acc,
               float *w, void *stream);
 
+/* ---------------------------------------------------------------------------
+ * Training backward (the paper envisions moving the TSDF bounds into training,
+ * Sec. 6 "Limitations and Future Work"; this is one step of it).
+ *
+ * composite_bwd: adjoint of composite() for the rgb output: given d_out_rgb
+ * [n_rays,3], writes per-sample d_f [S], d_grad_f [S,3] (through the NeuS
+ * opacity's cos = min(v.grad f, 0)) and d_rgb [S,3].  Inputs as in composite().
+ *
+ * rgb_loss: loss = (1/B) sum_rays |rgb - target|^2 (device scalar, reset by
+ * the call), d_rgb = 2 (rgb - target) / B.
+ *
+ * sdf_mlp_bwd: weight gradients of
+ *   sum_i (d_f_i f_i + d_grad_f_i . grad f_i + d_rgb_i . rgb_i)
+ *   + eik_lambda * mean_k (|grad f(eik_x_k)| - 1)^2
+ * over the samples p_i = o[ray_id_i] + t_i v[ray_id_i] (n_samples of them)
+ * and n_eik eikonal points, accumulated (+=) into d_params_sdf and
+ * d_params_color (host parameter layout, FP32, device).  Includes the
+ * second-order terms through grad f (colour input, opacity, eikonal).
+ * Activations are recomputed inside the call (none are kept from
+ * sdf_mlp_fwd).  d_f, d_grad_f may be NULL (zero).  eik_loss (optional,
+ * device float) receives the eikonal term.  FP32 only.  The products run in
+ * rocBLAS, which may allocate its own small workspace on first use.
+ * ws: sdf_mlp_bwd_ws_bytes(n_samples + n_eik). */
+int composite_bwd(const int32_t *offsets, int64_t n_rays, const float *v, const float *dt,
+                  const float *f, const float *grad_f, const float *rgb, float s,
+                  const float *d_out_rgb, float *d_f, float *d_grad_f, float *d_rgb,
+                  void *stream);
+int rgb_loss(const float *rgb, const float *target, int64_t n_rays, float *d_rgb, float *loss,
+             void *stream);
+int sdf_mlp_bwd_ws_bytes(const tsdfs_field *field, int64_t n_rows, size_t *bytes);
+int sdf_mlp_bwd(tsdfs_field *field, const float *o, const float *v, const float *t,
+                const int32_t *ray_id, int64_t n_samples, const float *eik_x, int64_t n_eik,
+                float eik_lambda, const float *d_f, const float *d_grad_f, const float *d_rgb,
+                int32_t precision, float *d_params_sdf, float *d_params_color, float *eik_loss,
+                void *ws, size_t ws_bytes, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -1,0 +1,72 @@
+"""torch.autograd.Function wrappers around the hand-written backward, and one
+TSDF-bounded training step (the paper's future-work direction of Sec. 6,
+moving the TSDF bounds into training).
+
+All arithmetic runs in libtsdfs.so: forward through sdf_mlp_fwd / composite,
+backward through composite_bwd / sdf_mlp_bwd (activations recomputed there).
+"""
+from __future__ import annotations
+
+import torch
+
+from . import ops
+from ._lib import FP32
+
+
+class FieldFn(torch.autograd.Function):
+    """(f, grad f, rgb) at p = o[ray_id] + t v[ray_id] as a function of the
+    network weights.  `sdf_w`, `col_w` are the device leaves holding the
+    parameters the field was created from; their gradients come from
+    sdf_mlp_bwd (FP32), including the second-order terms through grad f."""
+
+    @staticmethod
+    def forward(ctx, sdf_w, col_w, field, o, v, t, ray_id, precision=FP32):
+        f, g, rgb = field.forward(o, v, t, ray_id, precision=precision)
+        ctx.field = field
+        ctx.save_for_backward(o, v, t, ray_id)
+        return f, g, rgb
+
+    @staticmethod
+    def backward(ctx, d_f, d_g, d_rgb):
+        o, v, t, ray_id = ctx.saved_tensors
+        S = t.shape[0]
+        dev = t.device
+        d_f = d_f.contiguous() if d_f is not None else torch.zeros(S, device=dev)
+        d_g = d_g.contiguous() if d_g is not None else torch.zeros((S, 3), device=dev)
+        d_rgb = d_rgb.contiguous() if d_rgb is not None else torch.zeros((S, 3), device=dev)
+        d_sdf, d_col, _ = ctx.field.backward(o, v, t, ray_id, d_f, d_g, d_rgb)
+        return d_sdf, d_col, None, None, None, None, None, None
+
+
+class CompositeFn(torch.autograd.Function):
+    """Per-ray colour of Eq. 1 as a function of the samples' f, grad f, rgb."""
+
+    @staticmethod
+    def forward(ctx, f, g, rgb, offsets, v, t, dt, s):
+        out = ops.composite(offsets, v, t, dt, f, g, rgb, s)
+        ctx.save_for_backward(f, g, rgb, offsets, v, dt)
+        ctx.s = s
+        return out["rgb"]
+
+    @staticmethod
+    def backward(ctx, d_out):
+        f, g, rgb, offsets, v, dt = ctx.saved_tensors
+        d_f, d_g, d_c = ops.composite_bwd(offsets, v, dt, f, g, rgb, ctx.s, d_out.contiguous())
+        return d_f, d_g, d_c, None, None, None, None, None
+
+
+def train_step(renderer, o, v, target, eik_x, eik_lambda=0.1):
+    """One TSDF-bounded training step on a batch of rays (C ABI only):
+    Alg. 1 bounds -> placement -> field -> compositing -> photometric loss,
+    then the compositing adjoint and the network backward with the eikonal
+    term on eik_x.  Returns (loss_rgb, loss_eik, d_sdf, d_col, n_samples)."""
+    R = renderer
+    b = ops.ray_bounds(R.grid, R.flags, o, v, R.t_far)
+    p = ops.place(b, R.rho[0], R.rho[1], R.n_min, R.n_max, sync=True)
+    f, g, rgb = R.field.forward(o, v, p["t"], p["ray_id"], precision=FP32)
+    out = ops.composite(p["offsets"], v, p["t"], p["dt"], f, g, rgb, R.s)
+    loss, d_out = ops.rgb_loss(out["rgb"], target)
+    d_f, d_g, d_c = ops.composite_bwd(p["offsets"], v, p["dt"], f, g, rgb, R.s, d_out)
+    d_sdf, d_col, eik = R.field.backward(o, v, p["t"], p["ray_id"], d_f, d_g, d_c,
+                                         eik_x=eik_x, eik_lambda=eik_lambda)
+    return loss, eik, d_sdf, d_col, p["S"]

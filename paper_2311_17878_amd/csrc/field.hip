@@ -527,6 +527,43 @@ int tsdfs_field_create(const tsdfs_field_desc *d, const float *sdf_params,
     }
     P.wf = F->dev + wf_off;
     P.wrgb = F->dev + wrgb_off;
+    // plain parameter copies and layer offsets for the backward pass
+    F->n_lin = d->n_hidden + 1;
+    {
+        size_t off = 0;
+        for (int l = 0; l <= d->n_hidden; ++l) {
+            F->din[l] = l < d->n_hidden ? din[l] : W;
+            F->dout[l] = l < d->n_hidden ? dout[l] : 1 + d->n_feat;
+            F->w_off[l] = off;
+            off += (size_t)F->din[l] * F->dout[l];
+            F->b_off[l] = off;
+            off += F->dout[l];
+        }
+        F->n_sdf = off;
+        off = 0;
+        for (int l = 0; l <= d->col_hidden; ++l) {
+            F->cdin[l] = l == 0 ? cin : W;
+            F->cdout[l] = l < d->col_hidden ? W : 3;
+            F->cw_off[l] = off;
+            off += (size_t)F->cdin[l] * F->cdout[l];
+            F->cb_off[l] = off;
+            off += F->cdout[l];
+        }
+        F->n_col = off;
+        e = hipMalloc((void **)&F->params_sdf, (F->n_sdf + F->n_col) * sizeof(float));
+        if (e == hipSuccess)
+            e = hipMemcpy(F->params_sdf, sdf_params, F->n_sdf * sizeof(float), hipMemcpyHostToDevice);
+        F->params_col = F->params_sdf + F->n_sdf;
+        if (e == hipSuccess)
+            e = hipMemcpy(F->params_col, color_params, F->n_col * sizeof(float), hipMemcpyHostToDevice);
+        if (e != hipSuccess) {
+            set_error("parameter upload failed: %s", hipGetErrorString(e));
+            if (F->params_sdf) (void)hipFree(F->params_sdf);
+            (void)hipFree(F->dev);
+            delete F;
+            return TSDFS_EHIP;
+        }
+    }
     int dev = 0, n_cu = 0;
     (void)hipGetDevice(&dev);
     (void)hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev);
@@ -537,7 +574,9 @@ int tsdfs_field_create(const tsdfs_field_desc *d, const float *sdf_params,
 
 int tsdfs_field_destroy(tsdfs_field *F) {
     if (!F) return TSDFS_OK;
+    release_blas(F);
     if (F->dev) (void)hipFree(F->dev);
+    if (F->params_sdf) (void)hipFree(F->params_sdf);
     delete F;
     return TSDFS_OK;
 }

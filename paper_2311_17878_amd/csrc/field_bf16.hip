@@ -100,16 +100,40 @@ __device__ __forceinline__ float act_at(const __bf16 *act, int cc, int r) {
     return (float)act[cc * kStride + r];
 }
 
-// s_g[a][c] += sum_j eg[j][c] * d gamma_j / d x_hat_a (eg in global scratch, FP32)
-__device__ __forceinline__ void gamma_grad_reduce_b(const float *eg, int d_gamma,
-                                                    const float *s_xh, float *s_g) {
+// Encoding gamma_j(x_hat) and its derivative d gamma_j / d x_hat_a(j) for the
+// tile's samples, [j][sample] in FP32 scratch; one sincos per (frequency,
+// axis, sample).
+__device__ __forceinline__ void encode_tile(const float *s_xh, int d_gamma, float *gam,
+                                            float *jac) {
+    for (int idx = threadIdx.x; idx < d_gamma * kTile; idx += kBThreads) {
+        int j = idx / kTile, c = idx % kTile;
+        if (j < 3) {
+            gam[idx] = s_xh[j * kTile + c];
+            jac[idx] = 1.0f;
+            continue;
+        }
+        int jj = j - 3, k = jj / 6, rem = jj % 6;
+        if (rem >= 3) continue;   // the cos row is written with its sin row
+        int a = rem;
+        float sc = ldexpf(1.0f, k), sn, cs;
+        sincosf(sc * s_xh[a * kTile + c], &sn, &cs);
+        gam[idx] = sn;
+        jac[idx] = sc * cs;
+        gam[idx + 3 * kTile] = cs;
+        jac[idx + 3 * kTile] = -sc * sn;
+    }
+}
+
+__device__ __forceinline__ int gamma_axis_b(int j) { return j < 3 ? j : ((j - 3) % 6) % 3; }
+
+// s_g[a][c] += sum_j eg[j][c] * jac[j][c] over the rows j of axis a
+__device__ __forceinline__ void gamma_grad_reduce_b(const float *eg, const float *jac,
+                                                    int d_gamma, float *s_g) {
     for (int idx = threadIdx.x; idx < 3 * kTile; idx += kBThreads) {
         int a = idx / kTile, c = idx % kTile;
         float sum = 0.0f;
-        for (int j = 0; j < d_gamma; ++j) {
-            float d;
-            if (gamma_deriv(s_xh + c, j, d) == a) sum = fmaf(eg[j * kTile + c], d, sum);
-        }
+        for (int j = 0; j < d_gamma; ++j)
+            if (gamma_axis_b(j) == a) sum = fmaf(eg[j * kTile + c], jac[j * kTile + c], sum);
         s_g[a * kTile + c] += sum;
     }
 }
@@ -138,6 +162,8 @@ k_field_bf16(const Plan P, const float *__restrict__ o, const float *__restrict_
     float *slot = ws + (size_t)blockIdx.x * (P.n_hidden + 1) * kScratchLayer;
     uint4 *scr = (uint4 *)slot;                     // BF16 slots 0..n_hidden
     float *eg = slot + (size_t)P.n_hidden * kScratchLayer / 2 + 8 * 4 * 64 * 8;  // FP32 [64][128]
+    float *gam = eg + kGammaRows * kTile;           // FP32 [64][128]
+    float *jac = gam + kGammaRows * kTile;          // FP32 [64][128]
     const int feat_slot = P.n_hidden;
     const float rsqrt2 = 0.70710678118654752f;
     const float nbl2 = -P.beta * 1.44269504088896341f;   // -beta log2(e)
@@ -167,11 +193,13 @@ k_field_bf16(const Plan P, const float *__restrict__ o, const float *__restrict_
             }
         }
         __syncthreads();
+        encode_tile(s_xh, P.d_gamma, gam, jac);
+        __syncthreads();
         {
             const int K = P.fwd[0].K16 * 16;
             for (int idx = threadIdx.x; idx < K * kTile; idx += kBThreads) {
                 int c = idx / K, j = idx % K;
-                act[c * kStride + j] = (__bf16)(j < P.d_gamma ? gamma_value(s_xh + c, j) : 0.0f);
+                act[c * kStride + j] = (__bf16)(j < P.d_gamma ? gam[j * kTile + c] : 0.0f);
             }
         }
         __syncthreads();
@@ -223,7 +251,7 @@ k_field_bf16(const Plan P, const float *__restrict__ o, const float *__restrict_
             if (l + 1 == P.skip_at) {
                 for (int idx = threadIdx.x; idx < P.d_gamma * kTile; idx += kBThreads) {
                     int c = idx / P.d_gamma, j = idx % P.d_gamma;
-                    act[c * kStride + r + j] = (__bf16)(gamma_value(s_xh + c, j) * rsqrt2);
+                    act[c * kStride + r + j] = (__bf16)(gam[j * kTile + c] * rsqrt2);
                 }
                 r += P.d_gamma;
             }
@@ -355,7 +383,7 @@ k_field_bf16(const Plan P, const float *__restrict__ o, const float *__restrict_
             if (l > 0 && B.n_out < P.bwd[l - 1].K16 * 16) zero_rows_b(act, B.n_out, P.bwd[l - 1].K16 * 16);
             __syncthreads();
             if (skip || l == 0) {
-                gamma_grad_reduce_b(eg, P.d_gamma, s_xh, s_g);
+                gamma_grad_reduce_b(eg, jac, P.d_gamma, s_g);
                 __syncthreads();
             }
         }

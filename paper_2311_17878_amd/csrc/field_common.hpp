@@ -41,6 +41,8 @@ struct Plan {
     float brgb[3];
 };
 
+void release_blas(tsdfs_field *F);
+
 int launch_field_bf16(const Plan &P, int grid, const float *o, const float *v, const float *t,
                       const int32_t *ray_id, int64_t s_cap, const int64_t *s_count, float *f,
                       float *g, float *rgb, float *ws, hipStream_t stream);
@@ -50,8 +52,17 @@ int launch_field_bf16(const Plan &P, int grid, const float *o, const float *v, c
 struct tsdfs_field {
     tsdfs_field_desc desc;
     tsdfs::Plan plan;
-    float *dev = nullptr;   // all packed weights
-    int n_wg = 0;           // persistent grid size
+    float *dev = nullptr;        // all packed weights (FP32 + BF16 blocks)
+    int n_wg = 0;                // persistent grid size (compute units)
+    // plain row-major FP32 parameters (host layout) for the backward pass
+    float *params_sdf = nullptr, *params_col = nullptr;
+    size_t n_sdf = 0, n_col = 0;
+    int n_lin = 0;               // SDF linear layers (hidden + output)
+    int din[tsdfs::kMaxHidden + 1], dout[tsdfs::kMaxHidden + 1];
+    size_t w_off[tsdfs::kMaxHidden + 1], b_off[tsdfs::kMaxHidden + 1];
+    int cdin[tsdfs::kMaxColor + 1], cdout[tsdfs::kMaxColor + 1];
+    size_t cw_off[tsdfs::kMaxColor + 1], cb_off[tsdfs::kMaxColor + 1];
+    void *blas = nullptr;        // rocblas_handle, created on first backward
 };
 
 namespace tsdfs {
@@ -75,6 +86,8 @@ __device__ __forceinline__ int gamma_deriv(const float *xh, int j, float &d) {
     d = rem < 3 ? sc * cosf(x) : -sc * sinf(x);
     return a;
 }
+
+void release_blas(tsdfs_field *F);
 
 int launch_field_bf16(const Plan &P, int grid, const float *o, const float *v, const float *t,
                       const int32_t *ray_id, int64_t s_cap, const int64_t *s_count, float *f,

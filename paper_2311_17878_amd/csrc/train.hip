@@ -1,0 +1,610 @@
+// Training backward: compositing adjoint, photometric loss, and the
+// hand-derived weight gradients of the SDF + colour networks including the
+// second-order path weights -> grad f -> (colour input, opacity, eikonal).
+//
+// The network backward is organised layer by layer over all rows (samples
+// and eikonal points) with the activations recomputed inside the call:
+// plain row-major products go to rocBLAS (FP32), everything elementwise
+// (softplus and its first two derivatives, the encoding Jacobian, masks,
+// the adjoint bookkeeping) runs in the kernels below.
+#include <rocblas/rocblas.h>
+#include <math.h>
+#include <vector>
+
+#include "field_common.hpp"
+
+namespace tsdfs {
+
+template <typename F>
+__global__ void k_map(int64_t n, F f) {
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < n) f(i);
+}
+
+template <typename F>
+static void map(int64_t n, hipStream_t s, F f) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_map<F>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, f);
+}
+
+__device__ __forceinline__ float sig(float x) { return 1.0f / (1.0f + expf(-x)); }
+
+__device__ __forceinline__ float softplus_b(float z, float beta) {
+    return z > 0.0f ? z + log1pf(expf(-beta * z)) / beta : log1pf(expf(beta * z)) / beta;
+}
+
+// d gamma_j / d x_hat_a for the one axis a it depends on.
+__device__ __forceinline__ int gamma_axis(int j) { return j < 3 ? j : ((j - 3) % 6) % 3; }
+
+void release_blas(tsdfs_field *F) {
+    if (F && F->blas) {
+        rocblas_destroy_handle((rocblas_handle)F->blas);
+        F->blas = nullptr;
+    }
+}
+
+// Row-major C[M,N] = alpha op(A) op(B) + beta C (op(A): [M,K], op(B): [K,N]).
+static rocblas_status gemm_rm(rocblas_handle h, bool ta, bool tb, int M, int N, int K, float alpha,
+                              const float *A, int lda, const float *B, int ldb, float beta, float *C,
+                              int ldc) {
+    if (M == 0 || N == 0) return rocblas_status_success;
+    return rocblas_sgemm(h, tb ? rocblas_operation_transpose : rocblas_operation_none,
+                         ta ? rocblas_operation_transpose : rocblas_operation_none, N, M, K, &alpha,
+                         B, ldb, A, lda, &beta, C, ldc);
+}
+
+// y[N] += sum over rows of row-major A[R,N] (ld)
+static rocblas_status colsum(rocblas_handle h, int R, int N, const float *A, int ld,
+                             const float *ones, float *y) {
+    const float one = 1.0f;
+    return rocblas_sgemv(h, rocblas_operation_none, N, R, &one, A, ld, ones, 1, &one, y, 1);
+}
+
+// ------------------------------------------------------------- compositing --
+
+__device__ __forceinline__ float logsig_t(float x) {
+    return x >= 0.0f ? -log1pf(expf(-x)) : x - log1pf(expf(x));
+}
+
+// Adjoint of the NeuS compositing of rgb: given d rgb_out per ray, the
+// gradients w.r.t. each sample's f, grad f and rgb.
+__global__ void k_composite_bwd(const int32_t *__restrict__ offsets, int64_t n_rays,
+                                const float *__restrict__ v, const float *__restrict__ dt,
+                                const float *__restrict__ f, const float *__restrict__ g,
+                                const float *__restrict__ rgb, float s,
+                                const float *__restrict__ d_out, float *__restrict__ d_f,
+                                float *__restrict__ d_g, float *__restrict__ d_rgb) {
+    int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (r >= n_rays) return;
+    const int32_t j0 = offsets[r], j1 = offsets[r + 1];
+    const float vx = v[3 * r], vy = v[3 * r + 1], vz = v[3 * r + 2];
+    const float dc0 = d_out[3 * r], dc1 = d_out[3 * r + 1], dc2 = d_out[3 * r + 2];
+    // forward: total of w_i (dC . c_i) for the suffix sums
+    float logT = 0.0f, total = 0.0f;
+    for (int32_t j = j0; j < j1; ++j) {
+        float cosv = fminf(vx * g[3 * j] + vy * g[3 * j + 1] + vz * g[3 * j + 2], 0.0f);
+        float half = 0.5f * cosv * dt[j];
+        float L = fminf(logsig_t(s * (f[j] + half)) - logsig_t(s * (f[j] - half)), 0.0f);
+        float w = expf(logT) * (-expm1f(L));
+        total += w * (dc0 * rgb[3 * j] + dc1 * rgb[3 * j + 1] + dc2 * rgb[3 * j + 2]);
+        logT += L;
+    }
+    // backward: dL_j = -(1 - alpha_j) T_j (dC.c_j) + sum_{i>j} w_i (dC.c_i)
+    logT = 0.0f;
+    float done = 0.0f;   // sum_{i<=j} w_i (dC.c_i)
+    for (int32_t j = j0; j < j1; ++j) {
+        float gx = g[3 * j], gy = g[3 * j + 1], gz = g[3 * j + 2];
+        float cv = vx * gx + vy * gy + vz * gz;
+        float cosv = fminf(cv, 0.0f);
+        float fj = f[j], dtj = dt[j];
+        float half = 0.5f * cosv * dtj;
+        float xn = s * (fj + half), xp = s * (fj - half);
+        float L = fminf(logsig_t(xn) - logsig_t(xp), 0.0f);
+        float T = expf(logT);
+        float alpha = -expm1f(L);
+        float w = T * alpha;
+        float dcj = dc0 * rgb[3 * j] + dc1 * rgb[3 * j + 1] + dc2 * rgb[3 * j + 2];
+        done += w * dcj;
+        float dL = -(1.0f - alpha) * T * dcj + (total - done);
+        // L = logsig(xn) - logsig(xp), d logsig(x)/dx = sigmoid(-x)
+        float dxn = dL * sig(-xn), dxp = -dL * sig(-xp);
+        float dfn = s * dxn, dfp = s * dxp;
+        d_f[j] = dfn + dfp;
+        float dcos = (dfn - dfp) * 0.5f * dtj;
+        float dcv = cv < 0.0f ? dcos : 0.0f;
+        d_g[3 * j] = dcv * vx;
+        d_g[3 * j + 1] = dcv * vy;
+        d_g[3 * j + 2] = dcv * vz;
+        d_rgb[3 * j] = w * dc0;
+        d_rgb[3 * j + 1] = w * dc1;
+        d_rgb[3 * j + 2] = w * dc2;
+        logT += L;
+    }
+}
+
+// loss = (1/B) sum_rays |C - C*|^2 ; d C = 2 (C - C*) / B
+__global__ void k_rgb_loss(const float *__restrict__ rgb, const float *__restrict__ target,
+                           int64_t n_rays, float *__restrict__ d_rgb, float *__restrict__ loss) {
+    int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    float l = 0.0f;
+    if (r < n_rays) {
+        for (int a = 0; a < 3; ++a) {
+            float d = rgb[3 * r + a] - target[3 * r + a];
+            l += d * d;
+            d_rgb[3 * r + a] = 2.0f * d / (float)n_rays;
+        }
+    }
+    for (int off = 32; off > 0; off >>= 1) l += __shfl_xor(l, off);
+    if ((threadIdx.x & 63) == 0 && loss) atomicAdd(loss, l / (float)n_rays);
+}
+
+// ------------------------------------------------------- network backward --
+
+struct BwdBufs {
+    int R, S, P, W, dg, cin;
+    float *xh, *vr, *gam, *J;             // [R,3], [R,3], [R,dg], [R,dg]
+    float *X[kMaxHidden + 1];             // inputs of SDF layers (X[n_hidden] = H_last)
+    float *Z[kMaxHidden];                 // pre-activations (bias added)
+    float *D[kMaxHidden];                 // delta_l
+    float *E[kMaxHidden];                 // E_l = delta_{l+1} W_{l+1} (l < n_hidden - 1)
+    float *Eg0, *Eg4;                      // encoding rows of the reverse pass [R,dg]
+    float *Y;                              // output layer [R, 1 + n_feat]
+    float *g;                              // grad f [R,3]
+    float *Cin;                            // colour input [R, cin]
+    float *Zc[kMaxColor], *Hc[kMaxColor];  // colour pre/post activations
+    float *zo, *rgb;                       // [R,3]
+    float *gbar, *gbar_g;                  // [R,3], [R,dg]
+    float *Ybar;                           // [R, 1 + n_feat]
+    float *T0, *T1, *T2, *T3;             // scratch [R, max(cin, W+1)]
+    float *Z2[kMaxHidden];                 // second-order contributions
+    float *ones;                           // [R]
+    float *loss;                           // [2] eikonal loss (device)
+};
+
+static size_t carve(BwdBufs &b, const tsdfs_field *F, int R, char *base) {
+    const int W = F->desc.width, nh = F->desc.n_hidden;
+    const int dg = F->plan.d_gamma, cin = 9 + F->desc.n_feat;
+    const int wide = (cin > W + 1 ? cin : W + 1);
+    size_t off = 0;
+    auto take = [&](size_t n) -> float * {
+        float *p = base ? (float *)(base + off) : nullptr;
+        off += (n * sizeof(float) + 255) / 256 * 256;
+        return p;
+    };
+    b.R = R;
+    b.W = W;
+    b.dg = dg;
+    b.cin = cin;
+    b.xh = take((size_t)R * 3);
+    b.vr = take((size_t)R * 3);
+    b.gam = take((size_t)R * dg);
+    b.J = take((size_t)R * dg);
+    for (int l = 0; l <= nh; ++l) b.X[l] = l == 0 ? b.gam : take((size_t)R * W);
+    for (int l = 0; l < nh; ++l) {
+        b.Z[l] = take((size_t)R * W);
+        b.D[l] = take((size_t)R * W);
+        b.E[l] = take((size_t)R * W);
+        b.Z2[l] = take((size_t)R * W);
+    }
+    b.Eg0 = take((size_t)R * dg);
+    b.Eg4 = take((size_t)R * dg);
+    b.Y = take((size_t)R * (1 + F->desc.n_feat));
+    b.g = take((size_t)R * 3);
+    b.Cin = take((size_t)R * cin);
+    for (int l = 0; l < F->desc.col_hidden; ++l) {
+        b.Zc[l] = take((size_t)R * W);
+        b.Hc[l] = take((size_t)R * W);
+    }
+    b.zo = take((size_t)R * 3);
+    b.rgb = take((size_t)R * 3);
+    b.gbar = take((size_t)R * 3);
+    b.gbar_g = take((size_t)R * dg);
+    b.Ybar = take((size_t)R * (1 + F->desc.n_feat));
+    b.T0 = take((size_t)R * wide);
+    b.T1 = take((size_t)R * wide);
+    b.T2 = take((size_t)R * wide);
+    b.T3 = take((size_t)R * wide);
+    b.ones = take((size_t)R);
+    b.loss = take(2);
+    return off;
+}
+
+#define BLAS(call)                                                         \
+    do {                                                                   \
+        rocblas_status st_ = (call);                                       \
+        if (st_ != rocblas_status_success) {                               \
+            set_error("rocBLAS call failed (%d): %s", (int)st_, #call);    \
+            return TSDFS_EHIP;                                             \
+        }                                                                  \
+    } while (0)
+
+static int network_backward(tsdfs_field *F, const float *o, const float *v, const float *t,
+                            const int32_t *ray_id, int64_t S, const float *eik_x, int64_t P,
+                            float eik_lambda, const float *d_f, const float *d_grad,
+                            const float *d_rgb, float *gs, float *gc, char *ws, hipStream_t st,
+                            float *eik_loss_out) {
+    if (!F->blas) {
+        rocblas_handle h;
+        if (rocblas_create_handle(&h) != rocblas_status_success) {
+            set_error("rocblas_create_handle failed");
+            return TSDFS_EHIP;
+        }
+        F->blas = h;
+    }
+    rocblas_handle h = (rocblas_handle)F->blas;
+    BLAS(rocblas_set_stream(h, st));
+    BLAS(rocblas_set_pointer_mode(h, rocblas_pointer_mode_host));
+    const int R = (int)(S + P);
+    BwdBufs B;
+    carve(B, F, R, ws);
+    B.S = (int)S;
+    B.P = (int)P;
+    const tsdfs_field_desc &d = F->desc;
+    const Plan &PL = F->plan;
+    const int W = d.width, nh = d.n_hidden, dg = B.dg, cin = B.cin, nf = d.n_feat;
+    const int skip = d.skip_at;
+    const float beta = d.beta, scale = d.scale;
+    const float cx = d.center[0], cy = d.center[1], cz = d.center[2];
+    const float rs2 = 0.70710678118654752f;
+    const float *Ws = F->params_sdf, *Wc = F->params_col;
+    auto Wl = [&](int l) { return Ws + F->w_off[l]; };
+    auto bl = [&](int l) { return Ws + F->b_off[l]; };
+    auto gW = [&](int l) { return gs + F->w_off[l]; };
+    auto gb = [&](int l) { return gs + F->b_off[l]; };
+
+    // ---- inputs: x_hat, direction, encoding and its Jacobian; ones; loss = 0
+    {
+        float *xh = B.xh, *vr = B.vr, *gam = B.gam, *J = B.J, *ones = B.ones, *loss = B.loss;
+        const int Si = (int)S;
+        map((int64_t)R, st, [=] __device__(int64_t r) {
+            float p[3], vv[3];
+            if (r < Si) {
+                int64_t ray = ray_id[r];
+                for (int a = 0; a < 3; ++a) {
+                    vv[a] = v[3 * ray + a];
+                    p[a] = fmaf(t[r], vv[a], o[3 * ray + a]);
+                }
+            } else {
+                for (int a = 0; a < 3; ++a) {
+                    vv[a] = 0.0f;
+                    p[a] = eik_x[3 * (r - Si) + a];
+                }
+            }
+            float c[3] = {cx, cy, cz};
+            for (int a = 0; a < 3; ++a) {
+                float x = (p[a] - c[a]) / scale;
+                xh[3 * r + a] = x;
+                vr[3 * r + a] = vv[a];
+            }
+            for (int j = 0; j < dg; ++j) {
+                int a = gamma_axis(j);
+                float x = xh[3 * r + a];
+                if (j < 3) {
+                    gam[(int64_t)r * dg + j] = x;
+                    J[(int64_t)r * dg + j] = 1.0f;
+                } else {
+                    int k = (j - 3) / 6, rem = (j - 3) % 6;
+                    float sc = ldexpf(1.0f, k), y = sc * x;
+                    gam[(int64_t)r * dg + j] = rem < 3 ? sinf(y) : cosf(y);
+                    J[(int64_t)r * dg + j] = rem < 3 ? sc * cosf(y) : -sc * sinf(y);
+                }
+            }
+            ones[r] = 1.0f;
+            if (r < 2) loss[r] = 0.0f;
+        });
+    }
+    // ---- SDF forward
+    for (int l = 0; l < nh; ++l) {
+        const int in = F->din[l], out = F->dout[l];
+        BLAS(gemm_rm(h, false, true, R, out, in, 1.0f, B.X[l], in, Wl(l), in, 0.0f, B.Z[l], W));
+        float *Z = B.Z[l], *Xn = B.X[l + 1];
+        const float *bb = bl(l);
+        const bool to_skip = (l + 1 == skip);
+        const float hs = to_skip ? rs2 : 1.0f;
+        map((int64_t)R * out, st, [=] __device__(int64_t i) {
+            int64_t r = i / out;
+            int j = (int)(i - r * out);
+            float z = Z[r * W + j] + bb[j];
+            Z[r * W + j] = z;
+            Xn[r * W + j] = hs * softplus_b(z, beta);
+        });
+        if (to_skip) {
+            const float *gam = B.gam;
+            map((int64_t)R * dg, st, [=] __device__(int64_t i) {
+                int64_t r = i / dg;
+                int j = (int)(i - r * dg);
+                Xn[r * W + out + j] = rs2 * gam[i];
+            });
+        }
+    }
+    // output layer Y = X_last W_out^T + b_out
+    const int ny = 1 + nf;
+    BLAS(gemm_rm(h, false, true, R, ny, W, 1.0f, B.X[nh], W, Wl(nh), W, 0.0f, B.Y, ny));
+    {
+        float *Y = B.Y;
+        const float *bb = bl(nh);
+        map((int64_t)R * ny, st, [=] __device__(int64_t i) { Y[i] += bb[i % ny]; });
+    }
+    // ---- reverse pass: delta_{L-1} = w_f * softplus'(z), E_{l-1} = delta_l W_l
+    {
+        float *D = B.D[nh - 1];
+        const float *Z = B.Z[nh - 1], *wf = Wl(nh);
+        map((int64_t)R * W, st, [=] __device__(int64_t i) {
+            int j = (int)(i % W);
+            D[i] = wf[j] * sig(beta * Z[i]);
+        });
+    }
+    for (int l = nh - 1; l >= 1; --l) {
+        const int in = F->din[l], out = F->dout[l];
+        // E' = delta_l W_l : [R, in]
+        BLAS(gemm_rm(h, false, false, R, in, out, 1.0f, B.D[l], W, Wl(l), in, 0.0f, B.T0, W));
+        const int np = F->dout[l - 1];
+        const bool sk = (l == skip);
+        float *E = B.E[l - 1], *Dm = B.D[l - 1], *Eg4 = B.Eg4, *T0 = B.T0;
+        const float *Zm = B.Z[l - 1];
+        const float es = sk ? rs2 : 1.0f;
+        map((int64_t)R * in, st, [=] __device__(int64_t i) {
+            int64_t r = i / in;
+            int j = (int)(i - r * in);
+            float e = es * T0[r * W + j];
+            if (j < np) {
+                E[r * W + j] = e;
+                Dm[r * W + j] = e * sig(beta * Zm[r * W + j]);
+            } else {
+                Eg4[r * dg + (j - np)] = e;
+            }
+        });
+    }
+    // encoding rows from layer 0: Eg0 = delta_0 W_0 : [R, dg]
+    BLAS(gemm_rm(h, false, false, R, dg, F->dout[0], 1.0f, B.D[0], W, Wl(0), dg, 0.0f, B.Eg0, dg));
+    {
+        float *g = B.g;
+        const float *J = B.J, *Eg0 = B.Eg0, *Eg4 = B.Eg4;
+        const bool has_skip = skip > 0;
+        map((int64_t)R, st, [=] __device__(int64_t r) {
+            float acc3[3] = {0.f, 0.f, 0.f};
+            for (int j = 0; j < dg; ++j) {
+                float e = Eg0[r * dg + j] + (has_skip ? Eg4[r * dg + j] : 0.0f);
+                acc3[gamma_axis(j)] += e * J[r * dg + j];
+            }
+            for (int a = 0; a < 3; ++a) g[3 * r + a] = acc3[a];
+        });
+    }
+    // ---- colour forward
+    {
+        float *Cin = B.Cin;
+        const float *xh = B.xh, *vr = B.vr, *g = B.g, *Y = B.Y;
+        map((int64_t)R * cin, st, [=] __device__(int64_t i) {
+            int64_t r = i / cin;
+            int j = (int)(i - r * cin);
+            float x;
+            if (j < 3) x = xh[3 * r + j];
+            else if (j < 6) x = vr[3 * r + j - 3];
+            else if (j < 9) x = g[3 * r + j - 6];
+            else x = Y[r * ny + 1 + (j - 9)];
+            Cin[i] = x;
+        });
+    }
+    const int nc = d.col_hidden;
+    for (int l = 0; l < nc; ++l) {
+        const int in = F->cdin[l];
+        const float *X = l == 0 ? B.Cin : B.Hc[l - 1];
+        BLAS(gemm_rm(h, false, true, R, W, in, 1.0f, X, in, Wc + F->cw_off[l], in, 0.0f, B.Zc[l], W));
+        float *Z = B.Zc[l], *H = B.Hc[l];
+        const float *bb = Wc + F->cb_off[l];
+        map((int64_t)R * W, st, [=] __device__(int64_t i) {
+            float z = Z[i] + bb[i % W];
+            Z[i] = z;
+            H[i] = fmaxf(z, 0.0f);
+        });
+    }
+    BLAS(gemm_rm(h, false, true, R, 3, W, 1.0f, B.Hc[nc - 1], W, Wc + F->cw_off[nc], W, 0.0f, B.zo, 3));
+    // ---- colour backward: dz_out = d rgb * rgb (1 - rgb)
+    {
+        float *zo = B.zo, *rgb = B.rgb, *dz = B.T0;
+        const float *bb = Wc + F->cb_off[nc];
+        const int Si = (int)S;
+        map((int64_t)R * 3, st, [=] __device__(int64_t i) {
+            int64_t r = i / 3;
+            float c = sig(zo[i] + bb[i % 3]);
+            rgb[i] = c;
+            dz[i] = r < Si ? d_rgb[i] * c * (1.0f - c) : 0.0f;
+        });
+    }
+    // dW_c4 += dz^T H3 ; db += sum dz ; dH3 = dz W_c4
+    BLAS(gemm_rm(h, true, false, 3, W, R, 1.0f, B.T0, 3, B.Hc[nc - 1], W, 1.0f, gc + F->cw_off[nc], W));
+    BLAS(colsum(h, R, 3, B.T0, 3, B.ones, gc + F->cb_off[nc]));
+    BLAS(gemm_rm(h, false, false, R, W, 3, 1.0f, B.T0, 3, Wc + F->cw_off[nc], W, 0.0f, B.T1, W));
+    for (int l = nc - 1; l >= 0; --l) {
+        const int in = F->cdin[l];
+        float *dH = B.T1, *dZ = B.T2;
+        const float *Z = B.Zc[l];
+        map((int64_t)R * W, st, [=] __device__(int64_t i) { dZ[i] = Z[i] > 0.0f ? dH[i] : 0.0f; });
+        const float *X = l == 0 ? B.Cin : B.Hc[l - 1];
+        BLAS(gemm_rm(h, true, false, W, in, R, 1.0f, dZ, W, X, in, 1.0f, gc + F->cw_off[l], in));
+        BLAS(colsum(h, R, W, dZ, W, B.ones, gc + F->cb_off[l]));
+        // dX = dZ W_c : [R, in] (into T1, ld = in)
+        BLAS(gemm_rm(h, false, false, R, in, W, 1.0f, dZ, W, Wc + F->cw_off[l], in, 0.0f, B.T1, in));
+    }
+    // B.T1 now holds d Cin [R, cin]
+    // ---- g_bar = d grad (samples) + d Cin[:, 6:9] ; eikonal rows; encoding-space g_bar
+    {
+        float *gbar = B.gbar, *gbg = B.gbar_g, *loss = B.loss;
+        const float *dC = B.T1, *g = B.g, *J = B.J;
+        const int Si = (int)S;
+        const float lam = P > 0 ? eik_lambda / (float)P : 0.0f;
+        map((int64_t)R, st, [=] __device__(int64_t r) {
+            float gb3[3];
+            if (r < Si) {
+                for (int a = 0; a < 3; ++a)
+                    gb3[a] = (d_grad ? d_grad[3 * r + a] : 0.0f) + dC[r * cin + 6 + a];
+            } else {
+                float gx = g[3 * r], gy = g[3 * r + 1], gz = g[3 * r + 2];
+                float n = sqrtf(gx * gx + gy * gy + gz * gz);
+                float k = n > 0.0f ? 2.0f * lam * (n - 1.0f) / n : 0.0f;
+                gb3[0] = k * gx;
+                gb3[1] = k * gy;
+                gb3[2] = k * gz;
+                atomicAdd(loss, lam * (n - 1.0f) * (n - 1.0f));
+            }
+            for (int a = 0; a < 3; ++a) gbar[3 * r + a] = gb3[a];
+            for (int j = 0; j < dg; ++j) gbg[r * dg + j] = J[r * dg + j] * gb3[gamma_axis(j)];
+        });
+    }
+    {
+        float *Yb = B.Ybar;
+        const float *dC = B.T1;
+        const int Si = (int)S;
+        map((int64_t)R * ny, st, [=] __device__(int64_t i) {
+            int64_t r = i / ny;
+            int j = (int)(i - r * ny);
+            float y = 0.0f;
+            if (r < Si) y = j == 0 ? (d_f ? scale * d_f[r] : 0.0f) : dC[r * cin + 9 + (j - 1)];
+            Yb[i] = y;
+        });
+    }
+    // ---- second-order pass (adjoint of the reverse pass), forward in l
+    // delta_bar_0 = gbar_g W_0^T ; dW_0 += delta_0^T gbar_g
+    BLAS(gemm_rm(h, false, true, R, F->dout[0], dg, 1.0f, B.gbar_g, dg, Wl(0), dg, 0.0f, B.T0, W));
+    BLAS(gemm_rm(h, true, false, F->dout[0], dg, R, 1.0f, B.D[0], W, B.gbar_g, dg, 1.0f, gW(0), dg));
+    for (int l = 0; l < nh; ++l) {
+        // B.T0 holds delta_bar_l [R, dout[l]]
+        const int out = F->dout[l];
+        float *Eb = B.T1, *Z2 = B.Z2[l];
+        const float *db = B.T0, *Z = B.Z[l];
+        const bool top = (l == nh - 1);
+        const float *E = top ? Wl(nh) : B.E[l];   // top: w_f broadcast over rows
+        map((int64_t)R * out, st, [=] __device__(int64_t i) {
+            int64_t r = i / out;
+            int j = (int)(i - r * out);
+            float z = Z[r * W + j];
+            float sp = sig(beta * z);
+            float spp = beta * sp * (1.0f - sp);
+            float e = top ? E[j] : E[r * W + j];
+            float dbv = db[r * W + j];
+            Eb[r * W + j] = dbv * sp;          // E_bar_l (top: summed into w_f)
+            Z2[r * W + j] = dbv * e * spp;
+        });
+        if (top) {
+            // w_f_bar += column sums of delta_bar * softplus'(z)
+            BLAS(colsum(h, R, out, B.T1, W, B.ones, gW(nh)));
+            break;
+        }
+        const int ln = l + 1;
+        const int inn = F->din[ln], outn = F->dout[ln];
+        if (ln == skip) {
+            // E_bar'_l = [E_bar_l / sqrt2 | gbar_g / sqrt2]
+            float *Ep = B.T2;
+            const float *gbg = B.gbar_g;
+            map((int64_t)R * inn, st, [=] __device__(int64_t i) {
+                int64_t r = i / inn;
+                int j = (int)(i - r * inn);
+                Ep[r * W + j] = rs2 * (j < out ? Eb[r * W + j] : gbg[r * dg + (j - out)]);
+            });
+            BLAS(gemm_rm(h, false, true, R, outn, inn, 1.0f, B.T2, W, Wl(ln), inn, 0.0f, B.T0, W));
+            BLAS(gemm_rm(h, true, false, outn, inn, R, 1.0f, B.D[ln], W, B.T2, W, 1.0f, gW(ln), inn));
+        } else {
+            BLAS(gemm_rm(h, false, true, R, outn, inn, 1.0f, B.T1, W, Wl(ln), inn, 0.0f, B.T0, W));
+            BLAS(gemm_rm(h, true, false, outn, inn, R, 1.0f, B.D[ln], W, B.T1, W, 1.0f, gW(ln), inn));
+        }
+    }
+    // ---- first-order pass (ordinary backprop of the forward, with the
+    // second-order contributions Z2 injected at every hidden layer)
+    BLAS(gemm_rm(h, true, false, ny, W, R, 1.0f, B.Ybar, ny, B.X[nh], W, 1.0f, gW(nh), W));
+    BLAS(colsum(h, R, ny, B.Ybar, ny, B.ones, gb(nh)));
+    BLAS(gemm_rm(h, false, false, R, W, ny, 1.0f, B.Ybar, ny, Wl(nh), W, 0.0f, B.T0, W));
+    float hbar_scale = 1.0f;   // 1/sqrt2 when T0 came through the skip input
+    for (int l = nh - 1; l >= 0; --l) {
+        const int in = F->din[l], out = F->dout[l];
+        float *Zb = B.T1;
+        const float *Hb = B.T0, *Z = B.Z[l], *Z2 = B.Z2[l];
+        const float hsc = hbar_scale;
+        map((int64_t)R * out, st, [=] __device__(int64_t i) {
+            int64_t r = i / out;
+            int j = (int)(i - r * out);
+            Zb[r * W + j] = hsc * Hb[r * W + j] * sig(beta * Z[r * W + j]) + Z2[r * W + j];
+        });
+        BLAS(gemm_rm(h, true, false, out, in, R, 1.0f, B.T1, W, B.X[l], in, 1.0f, gW(l), in));
+        BLAS(colsum(h, R, out, B.T1, W, B.ones, gb(l)));
+        if (l > 0) {
+            BLAS(gemm_rm(h, false, false, R, in, out, 1.0f, B.T1, W, Wl(l), in, 0.0f, B.T0, W));
+            hbar_scale = (l == skip) ? rs2 : 1.0f;
+        }
+    }
+    if (eik_loss_out) {
+        const float *loss = B.loss;
+        map(1, st, [=] __device__(int64_t) { *eik_loss_out = loss[0]; });
+    }
+    return TSDFS_OK;
+}
+
+}  // namespace tsdfs
+
+using namespace tsdfs;
+
+extern "C" {
+
+int sdf_mlp_bwd_ws_bytes(const tsdfs_field *F, int64_t n_rows, size_t *bytes) {
+    TSDFS_CHECK_ARG(F && bytes && n_rows >= 0, "bad arguments");
+    BwdBufs b;
+    *bytes = carve(b, F, (int)n_rows, nullptr);
+    return TSDFS_OK;
+}
+
+int sdf_mlp_bwd(tsdfs_field *F, const float *o, const float *v, const float *t,
+                const int32_t *ray_id, int64_t n_samples, const float *eik_x, int64_t n_eik,
+                float eik_lambda, const float *d_f, const float *d_grad_f, const float *d_rgb,
+                int32_t precision, float *d_params_sdf, float *d_params_color, float *eik_loss,
+                void *ws, size_t ws_bytes, void *stream) {
+    TSDFS_CHECK_ARG(F != nullptr, "field is NULL");
+    TSDFS_CHECK_ARG(n_samples >= 0 && n_eik >= 0, "negative sizes");
+    TSDFS_CHECK_ARG(n_samples + n_eik < ((int64_t)1 << 31) / 512, "too many rows");
+    if (precision != TSDFS_FP32) {
+        set_error("sdf_mlp_bwd: only FP32 is supported");
+        return TSDFS_EUNSUPPORTED;
+    }
+    TSDFS_CHECK_ARG(d_params_sdf && d_params_color, "NULL gradient output");
+    if (n_samples + n_eik == 0) return TSDFS_OK;
+    TSDFS_CHECK_ARG(n_samples == 0 || (o && v && t && ray_id && d_rgb), "NULL sample array");
+    TSDFS_CHECK_ARG(n_eik == 0 || eik_x, "NULL eikonal points");
+    size_t need;
+    sdf_mlp_bwd_ws_bytes(F, n_samples + n_eik, &need);
+    TSDFS_CHECK_ARG(ws && ws_bytes >= need, "workspace too small (%zu < %zu)", ws_bytes, need);
+    int rc = network_backward(F, o, v, t, ray_id, n_samples, eik_x, n_eik, eik_lambda, d_f,
+                              d_grad_f, d_rgb, d_params_sdf, d_params_color, (char *)ws,
+                              as_stream(stream), eik_loss);
+    if (rc) return rc;
+    TSDFS_LAUNCH_CHECK();
+    return TSDFS_OK;
+}
+
+int composite_bwd(const int32_t *offsets, int64_t n_rays, const float *v, const float *dt,
+                  const float *f, const float *grad_f, const float *rgb, float s,
+                  const float *d_out_rgb, float *d_f, float *d_grad_f, float *d_rgb,
+                  void *stream) {
+    TSDFS_CHECK_ARG(n_rays >= 0 && s > 0.0f, "bad arguments");
+    if (n_rays == 0) return TSDFS_OK;
+    TSDFS_CHECK_ARG(offsets && v && dt && f && grad_f && rgb && d_out_rgb && d_f && d_grad_f && d_rgb,
+                    "NULL array argument");
+    hipLaunchKernelGGL(k_composite_bwd, dim3((unsigned)((n_rays + 255) / 256)), dim3(256), 0,
+                       as_stream(stream), offsets, n_rays, v, dt, f, grad_f, rgb, s, d_out_rgb,
+                       d_f, d_grad_f, d_rgb);
+    TSDFS_LAUNCH_CHECK();
+    return TSDFS_OK;
+}
+
+int rgb_loss(const float *rgb, const float *target, int64_t n_rays, float *d_rgb, float *loss,
+             void *stream) {
+    TSDFS_CHECK_ARG(n_rays >= 0, "bad arguments");
+    TSDFS_CHECK_ARG(loss != nullptr, "NULL loss");
+    hipStream_t st = as_stream(stream);
+    map(1, st, [=] __device__(int64_t) { *loss = 0.0f; });
+    if (n_rays == 0) return TSDFS_OK;
+    TSDFS_CHECK_ARG(rgb && target && d_rgb, "NULL array argument");
+    hipLaunchKernelGGL(k_rgb_loss, dim3((unsigned)((n_rays + 255) / 256)), dim3(256), 0, st, rgb,
+                       target, n_rays, d_rgb, loss);
+    TSDFS_LAUNCH_CHECK();
+    return TSDFS_OK;
+}
+
+}  // extern "C"

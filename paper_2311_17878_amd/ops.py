@@ -195,6 +195,26 @@ class Field:
                                      _stream()))
         return f[:S], (g[:S] if full else None), (rgb[:S] if full else None)
 
+    def backward(self, o, v, t, ray_id, d_f, d_grad, d_rgb, eik_x=None, eik_lambda=0.0,
+                 d_sdf=None, d_col=None):
+        """Accumulate weight gradients (FP32) into d_sdf / d_col (allocated
+        zeroed when None); returns (d_sdf, d_col, eikonal loss tensor)."""
+        d = _dev()
+        S = t.shape[0] if t is not None else 0
+        P = eik_x.shape[0] if eik_x is not None else 0
+        if d_sdf is None:
+            d_sdf = torch.zeros(self._sp.size, dtype=torch.float32, device=d)
+        if d_col is None:
+            d_col = torch.zeros(self._cp.size, dtype=torch.float32, device=d)
+        b = ctypes.c_size_t(0)
+        L.check(L.load().sdf_mlp_bwd_ws_bytes(self.handle, S + P, ctypes.byref(b)))
+        ws = torch.empty(max(b.value, 256), dtype=torch.uint8, device=d)
+        eik = torch.zeros(1, dtype=torch.float32, device=d)
+        L.check(L.load().sdf_mlp_bwd(self.handle, _p(o), _p(v), _p(t), _p(ray_id), S, _p(eik_x), P,
+                                     float(eik_lambda), _p(d_f), _p(d_grad), _p(d_rgb), L.FP32,
+                                     _p(d_sdf), _p(d_col), _p(eik), _p(ws), ws.numel(), _stream()))
+        return d_sdf, d_col, eik
+
     def close(self):
         if self.handle:
             L.load().tsdfs_field_destroy(self.handle)
@@ -219,3 +239,23 @@ def composite(offsets, v, t, dt, f, grad, rgb, s, want_w=False):
                                float(s), _p(out["rgb"]), _p(out["depth"]), _p(out["normal"]),
                                _p(out["acc"]), _p(out["w"]), _stream()))
     return out
+
+
+def composite_bwd(offsets, v, dt, f, grad, rgb, s, d_out_rgb):
+    S = f.shape[0]
+    d = _dev()
+    d_f = torch.empty(max(S, 1), dtype=torch.float32, device=d)
+    d_g = torch.empty((max(S, 1), 3), dtype=torch.float32, device=d)
+    d_c = torch.empty((max(S, 1), 3), dtype=torch.float32, device=d)
+    L.check(L.load().composite_bwd(_p(offsets), offsets.shape[0] - 1, _p(v), _p(dt), _p(f),
+                                   _p(grad), _p(rgb), float(s), _p(d_out_rgb), _p(d_f), _p(d_g),
+                                   _p(d_c), _stream()))
+    return d_f[:S], d_g[:S], d_c[:S]
+
+
+def rgb_loss(rgb, target):
+    R = rgb.shape[0]
+    d_rgb = torch.empty_like(rgb)
+    loss = torch.empty(1, dtype=torch.float32, device=_dev())
+    L.check(L.load().rgb_loss(_p(rgb), _p(target), R, _p(d_rgb), _p(loss), _stream()))
+    return loss, d_rgb

@@ -1,0 +1,192 @@
+"""GPU parity of the training backward (compositing adjoint, network weight
+gradients with the second-order terms, one TSDF-bounded training step)
+against the FP64 oracle's reverse-mode gradients and central differences."""
+import numpy as np
+import pytest
+import torch
+
+from synth.configs import get_config
+from oracle import tsdf as OT, field as OF, render as OR, train as OTR
+
+pytestmark = pytest.mark.gpu
+
+
+def dev(a):
+    return torch.as_tensor(np.ascontiguousarray(a)).cuda()
+
+
+def host(t):
+    return t.detach().cpu().numpy()
+
+
+def make_field(cfg):
+    from paper_2311_17878_amd import ops
+    return ops.Field(cfg.sdf.width, cfg.sdf.n_hidden, cfg.sdf.pe_freqs, cfg.sdf.skip_at,
+                     cfg.sdf.n_feat, cfg.color.n_hidden, cfg.sdf.beta, cfg.in_center,
+                     cfg.in_scale, cfg.sdf_params(), cfg.color_params())
+
+
+def compare(name, got, ref):
+    got = np.asarray(got, np.float64)
+    ref = np.asarray(ref, np.float64)
+    cos = float(got @ ref / (np.linalg.norm(got) * np.linalg.norm(ref)))
+    rel = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+    print(f"{name}: cosine {cos:.9f}  rel L2 {rel:.3e}")
+    return cos, rel
+
+
+@pytest.fixture(scope="module")
+def c1_volume():
+    cfg = get_config("c1")
+    g = cfg.grid
+    o, v, d = cfg.integration_rays()
+    st = OT.integrate(g, o, v, d)
+    fl = OT.flags(g, OT.finalize(g, st))
+    return cfg, fl, (o, v, d)
+
+
+def test_composite_bwd_matches_oracle(c1_volume):
+    from paper_2311_17878_amd import ops
+    cfg, fl, _ = c1_volume
+    ro, rv = cfg.render_rays()
+    b = OT.bounds(cfg.grid, fl, ro, rv)
+    s = cfg.sampling
+    p = OT.place(b["t_n"], b["t_f"], b["n_vox"], b["status"], s.rho_num, s.rho_den, s.n_min, s.n_max)
+    rng = np.random.default_rng(3)
+    S = p["t"].size
+    f = rng.normal(0, 0.03, S).astype(np.float32)
+    gr = rng.normal(0, 1, (S, 3)).astype(np.float32)
+    rgb = rng.uniform(0, 1, (S, 3)).astype(np.float32)
+    dC = rng.normal(0, 1, (ro.shape[0], 3)).astype(np.float32)
+    t32, dt32 = p["t"].astype(np.float32), p["dt"].astype(np.float32)
+    T = lambda a: torch.tensor(np.asarray(a, np.float64), requires_grad=True)
+    ft, gt, ct = T(f), T(gr), T(rgb)
+    out = OR.composite_t(p["offsets"], rv, torch.tensor(t32.astype(np.float64)),
+                         torch.tensor(dt32.astype(np.float64)), ft, gt, ct, cfg.neus_s)
+    (out["rgb"] * torch.tensor(dC.astype(np.float64))).sum().backward()
+    df, dg, dc = ops.composite_bwd(dev(p["offsets"].astype(np.int32)), dev(rv), dev(dt32), dev(f),
+                                   dev(gr), dev(rgb), cfg.neus_s, dev(dC))
+    for name, a, bref in (("d_f", df, ft.grad), ("d_grad", dg, gt.grad), ("d_rgb", dc, ct.grad)):
+        e = np.abs(host(a) - bref.numpy()).max()
+        scale = np.abs(bref.numpy()).max()
+        print(name, "max abs err", e, "max |ref|", scale)
+        assert e <= 1e-4 * max(scale, 1.0), name
+
+
+def test_network_backward_matches_oracle(c1_volume):
+    """Weight gradients of sum(d_f f + d_g . grad f + d_rgb . rgb) + the
+    eikonal term, with seeded upstream gradients."""
+    cfg, fl, _ = c1_volume
+    ro, rv = cfg.render_rays()
+    b = OT.bounds(cfg.grid, fl, ro, rv)
+    s = cfg.sampling
+    p = OT.place(b["t_n"], b["t_f"], b["n_vox"], b["status"], s.rho_num, s.rho_den, s.n_min, s.n_max)
+    keep = np.flatnonzero(p["ray_id"] < 400)
+    t32 = p["t"][keep].astype(np.float32)
+    rid = p["ray_id"][keep].astype(np.int32)
+    S = t32.size
+    rng = np.random.default_rng(4)
+    d_f = rng.normal(0, 1, S).astype(np.float32)
+    d_g = rng.normal(0, 1, (S, 3)).astype(np.float32)
+    d_c = rng.normal(0, 1, (S, 3)).astype(np.float32)
+    eik = cfg.eikonal_points(64, seed=5)
+    lam = 0.1
+    F = make_field(cfg)
+    gs, gc, el = F.backward(dev(ro), dev(rv), dev(t32), dev(rid), dev(d_f), dev(d_g), dev(d_c),
+                            eik_x=dev(eik), eik_lambda=lam)
+    torch.cuda.synchronize()
+    # oracle: reverse mode in FP64 of the same scalar
+    sl = OF.as_layers(cfg.sdf_params(), cfg.sdf.layer_dims(), requires_grad=True)
+    cl = OF.as_layers(cfg.color_params(), cfg.color.layer_dims(), requires_grad=True)
+    o64, v64 = ro.astype(np.float64), rv.astype(np.float64)
+    vv = torch.tensor(v64[rid])
+    pts = torch.tensor(o64[rid]) + torch.tensor(t32.astype(np.float64))[:, None] * vv
+    f, g, c = OF.field(cfg, sl, cl, pts, vv, create_graph=True)
+    L = ((f * torch.tensor(d_f.astype(np.float64))).sum() + (g * torch.tensor(d_g.astype(np.float64))).sum()
+         + (c * torch.tensor(d_c.astype(np.float64))).sum())
+    x = torch.tensor(eik.astype(np.float64), requires_grad=True)
+    fe, _, _ = OF.sdf_forward(cfg.sdf, sl, x, cfg.in_center, cfg.in_scale)
+    (ge,) = torch.autograd.grad(fe.sum(), x, create_graph=True)
+    l_eik = lam * ((torch.linalg.norm(ge, dim=-1) - 1) ** 2).mean()
+    L = L + l_eik
+    ps = [q for W, b_ in sl for q in (W, b_)]
+    pc = [q for W, b_ in cl for q in (W, b_)]
+    grads = torch.autograd.grad(L, ps + pc)
+    ref_s = torch.cat([q.reshape(-1) for q in grads[:len(ps)]]).numpy()
+    ref_c = torch.cat([q.reshape(-1) for q in grads[len(ps):]]).numpy()
+    assert abs(float(el.item()) - float(l_eik)) <= 1e-5 * max(1.0, float(l_eik))
+    cs, rs = compare("sdf grads", host(gs), ref_s)
+    cc, rc = compare("colour grads", host(gc), ref_c)
+    assert cs >= 0.99999 and rs <= 1e-4
+    assert cc >= 0.99999 and rc <= 1e-4
+
+
+def _train_batch(cfg, n_rays, n_eik, seed):
+    ro, rv, target = cfg.training_batch(n_rays, seed)
+    return ro, rv, target, cfg.eikonal_points(n_eik, seed)
+
+
+@pytest.mark.parametrize("name,n_rays,n_eik", [("c1", 96, 64), ("c2", 64, 64)])
+def test_train_step_matches_oracle_and_fd(name, n_rays, n_eik):
+    from paper_2311_17878_amd import ops
+    from paper_2311_17878_amd.pipeline import TsdfRenderer
+    from paper_2311_17878_amd.autograd import train_step
+    cfg = get_config(name)
+    g, s = cfg.grid, cfg.sampling
+    o, v, d = cfg.integration_rays()
+    grid = ops.make_grid(g.n, g.lo, g.h, g.d_t, g.d_s, g.nb_radius, g.m_consec)
+    F = make_field(cfg)
+    R = TsdfRenderer(grid, F, s.rho_num, s.rho_den, s.n_min, s.n_max, cfg.neus_s)
+    R.integrate(dev(o), dev(v), dev(d), batch=1 << 24)
+    R.finalize(want_v=False)
+    ro, rv, target, eik = _train_batch(cfg, n_rays, n_eik, seed=7)
+    loss, leik, gs, gc, S = train_step(R, dev(ro), dev(rv), dev(target), dev(eik), eik_lambda=0.1)
+    torch.cuda.synchronize()
+    # the oracle's own volume, bounds and placement for the same rays
+    fl = host(R.flags)      # bit-exact with the oracle's flags (checked in the parity suites)
+    if name == "c1":
+        st = OT.integrate(g, o, v, d)
+        fl_o = OT.flags(g, OT.finalize(g, st)).ravel()
+    else:
+        import os
+        gold = np.load(os.path.join(os.path.dirname(__file__), "golden", "c2_volume.npz"))
+        N = int(gold["n_vox"])
+        fl_o = (np.unpackbits(gold["flag0"])[:N] | (np.unpackbits(gold["flag1"])[:N] << 1)).astype(np.uint8)
+    assert np.array_equal(fl, fl_o)
+    b = OT.bounds(g, fl_o, ro, rv)
+    p = OT.place(b["t_n"], b["t_f"], b["n_vox"], b["status"], s.rho_num, s.rho_den, s.n_min, s.n_max)
+    assert S == p["offsets"][-1]
+    batch = dict(o=ro, v=rv, offsets=p["offsets"], t=p["t"], dt=p["dt"], target=target, eik_x=eik,
+                 eik_lambda=0.1)
+    L, ref_s, ref_c = OTR.loss_and_grads(cfg, cfg.sdf_params(), cfg.color_params(), batch)
+    got_L = float(loss.item() + leik.item())
+    print(f"{name}: loss gpu {got_L:.9f} oracle {L:.9f}; samples {S}")
+    assert abs(got_L - L) <= 1e-5 * max(1.0, abs(L))
+    cs, rs = compare(f"{name} sdf grads", host(gs), ref_s)
+    cc, rc = compare(f"{name} colour grads", host(gc), ref_c)
+    assert cs >= 0.99999 and rs <= 1e-3
+    assert cc >= 0.99999 and rc <= 1e-3
+    if name != "c1":
+        return
+    # central differences (FP64 oracle loss) on 32 seeded weights
+    rng = np.random.default_rng(11)
+    gs_h, gc_h = host(gs), host(gc)
+    ps64, pc64 = cfg.sdf_params().astype(np.float64), cfg.color_params().astype(np.float64)
+    picks = [("s", i) for i in rng.choice(np.flatnonzero(np.abs(ref_s) > 1e-3 * np.abs(ref_s).max()), 24, replace=False)]
+    picks += [("c", i) for i in rng.choice(np.flatnonzero(np.abs(ref_c) > 1e-3 * np.abs(ref_c).max()), 8, replace=False)]
+    worst4 = worst6 = 0.0
+    for which, i in picks:
+        fds = {}
+        for hstep in (1e-4, 1e-6):
+            a, b_ = ps64.copy(), pc64.copy()
+            tgt = a if which == "s" else b_
+            tgt[i] += hstep
+            lp = OTR.loss_value(cfg, a, b_, batch)
+            tgt[i] -= 2 * hstep
+            lm = OTR.loss_value(cfg, a, b_, batch)
+            fds[hstep] = (lp - lm) / (2 * hstep)
+        gpu = gs_h[i] if which == "s" else gc_h[i]
+        worst4 = max(worst4, abs(gpu - fds[1e-4]) / max(abs(fds[1e-6]), 1e-12))
+        worst6 = max(worst6, abs(gpu - fds[1e-6]) / max(abs(fds[1e-6]), 1e-12))
+    print(f"FD check on 32 weights: max rel err vs h=1e-4 {worst4:.3e}, vs h=1e-6 {worst6:.3e}")
+    assert worst6 <= 1e-3
