@@ -80,7 +80,18 @@ def main():
     ap.add_argument("--cpu-rays", type=int, default=1024)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-hs", action="store_true")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run a device-to-device copy of MIB MiB (to scale HBM counters)")
     args = ap.parse_args()
+    if args.copy_calibration:
+        import torch
+        n = args.copy_calibration * (1 << 20) // 4
+        a = torch.ones(n, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_mib": args.copy_calibration}))
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU design is "
               "described in DESIGN.md but not built", file=sys.stderr)
@@ -204,6 +215,53 @@ def main():
             "paper_context": "1.445e6 rays/s (0.692 us/ray, 39.0 M rays in 27.02 s, GPU unnamed)",
         },
     }
+
+    # ---- the other precision on the same step
+    other = _lib.FP32 if prec == _lib.BF16 else _lib.BF16
+    oname = "f32" if other == _lib.FP32 else "bf16"
+    R.precision = other
+    for _ in range(args.warmup):
+        R.render(ro_d, rv_d)
+    ev_o = {}
+    torch.cuda.synchronize()
+    start.record()
+    for _ in range(args.steps):
+        R.render(ro_d, rv_d, events=ev_o)
+    end.record()
+    torch.cuda.synchronize()
+    R.precision = prec
+    ms_o = start.elapsed_time(end) / args.steps
+    field_o = float(np.mean([a.elapsed_time(b) for a, b in ev_o["field"]]))
+    ach_o = S * fl_sample / (field_o * 1e-3) / 1e12
+    result[oname] = {
+        "ms_per_step": ms_o, "rays_per_s": n_rays / (ms_o * 1e-3), "field_ms": field_o,
+        "roofline": {"kernel": "k_field_bf16" if other == _lib.BF16 else "k_field_fp32",
+                     "bound": "mfma", "achieved": ach_o, "peak": PEAK_TFLOPS[oname],
+                     "unit": "TFLOP/s", "frac": ach_o / PEAK_TFLOPS[oname]},
+    }
+    log(f"{oname}: {ms_o:.3f} ms/step")
+
+    # ---- one TSDF-bounded training step (8192 rays + 8192 eikonal points)
+    if cfg.name in ("c2", "c3", "c4"):
+        from paper_2311_17878_amd.autograd import train_step
+        tro, trv, ttarget = cfg.training_batch(8192, seed=0)
+        teik = cfg.eikonal_points(8192, seed=0)
+        tro, trv, ttarget, teik = dev(tro), dev(trv), dev(ttarget), dev(teik)
+        out_t = train_step(R, tro, trv, ttarget, teik)   # warm-up (rocBLAS set-up)
+        torch.cuda.synchronize()
+        n_t = max(1, min(args.steps, 5))
+        start.record()
+        for _ in range(n_t):
+            out_t = train_step(R, tro, trv, ttarget, teik)
+        end.record()
+        torch.cuda.synchronize()
+        tms = start.elapsed_time(end) / n_t
+        result["train_step"] = {
+            "rays": 8192, "eikonal_points": 8192, "samples": int(out_t[4]), "ms_per_step": tms,
+            "loss_rgb": float(out_t[0].item()), "loss_eik": float(out_t[1].item()),
+            "precision": "f32 (forward and backward)",
+        }
+        log(f"train step: {tms:.2f} ms")
 
     if not args.no_hs:
         for _ in range(1):

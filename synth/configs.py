@@ -267,8 +267,10 @@ def _c5():
     return Config(
         name="c5",
         grid=Grid((512, 512, 512), (-0.5, -0.5, -0.5), h, 5 * h, h),
-        sdf=SdfNet(), color=ColorNet(),
-        in_center=(6.0, 4.0, 1.5), in_scale=6.0,
+        # inside-out geometric-init sphere of radius 1.5 m centred at the
+        # panorama's viewpoint (median hit distance 1.47 m)
+        sdf=SdfNet(inside_out=True), color=ColorNet(),
+        in_center=(11.11, 2.61, 1.39), in_scale=3.0,
         sampling=Sampling(1, 2, 1, 64),
         precision="bf16",
         build_scene=_scene_c5,
