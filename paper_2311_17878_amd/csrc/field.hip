@@ -380,10 +380,11 @@ static uint16_t to_bf16(float x) {
     return (uint16_t)(u >> 16);
 }
 
-// Pack M as the A operand of v_mfma_f32_32x32x16_bf16:
-// P[((t*K16 + kk)*64 + lane)*8 + j] = bf16(M[t*32 + lane%32][16 kk + 8 (lane/32) + j]).
-static void pack_a_bf16(std::vector<uint16_t> &out, const float *M, int n_out, int K, int ld,
-                        bool transpose) {
+// Pack an n_out x K matrix given by m(r, k) as the A operand of
+// v_mfma_f32_32x32x16_bf16:
+// P[((t*K16 + kk)*64 + lane)*8 + j] = bf16(m(t*32 + lane%32, 16 kk + 8 (lane/32) + j)).
+template <class M>
+static void pack_a_bf16(std::vector<uint16_t> &out, int n_out, int K, M m) {
     int K16 = (K + 15) / 16, nt = (n_out + 31) / 32;
     size_t base = out.size();
     out.resize(base + (size_t)nt * K16 * 64 * 8, 0);
@@ -393,8 +394,7 @@ static void pack_a_bf16(std::vector<uint16_t> &out, const float *M, int n_out, i
                 for (int j = 0; j < 8; ++j) {
                     int r = t * 32 + (lane & 31), k = 16 * kk + 8 * (lane >> 5) + j;
                     if (r < n_out && k < K)
-                        out[base + ((size_t)(t * K16 + kk) * 64 + lane) * 8 + j] =
-                            to_bf16(transpose ? M[(size_t)k * ld + r] : M[(size_t)r * ld + k]);
+                        out[base + ((size_t)(t * K16 + kk) * 64 + lane) * 8 + j] = to_bf16(m(r, k));
                 }
 }
 
@@ -454,21 +454,31 @@ int tsdfs_field_create(const tsdfs_field_desc *d, const float *sdf_params,
     // offsets into the packed host buffers, resolved to device pointers below
     std::vector<float> buf;
     std::vector<uint16_t> bbuf;
-    struct Ref { Layer *L; size_t w, wb, b; bool has_b; };
+    struct Ref { Layer *L; size_t w, b; bool has_b; };
     std::vector<Ref> refs;
     auto add_layer = [&](Layer *L, const float *M, int n_out, int K, int ld, bool tr,
                          const float *bias) {
         L->K8 = round8(K);
-        L->K16 = (K + 15) / 16;
         L->n_tiles = (n_out + 31) / 32;
         L->n_out = n_out;
         size_t w = buf.size();
         pack_a(buf, M, n_out, K, ld, tr);
-        size_t wb = bbuf.size();
-        pack_a_bf16(bbuf, M, n_out, K, ld, tr);
         size_t b = buf.size();
         if (bias) pack_bias(buf, bias, n_out);
-        refs.push_back({L, w, wb, b, bias != nullptr});
+        refs.push_back({L, w, b, bias != nullptr});
+    };
+    // BF16 layers: weights m(r, k) into bbuf, bias (host vector) into buf
+    struct BRef { BLayer *L; size_t w, b; bool has_b; };
+    std::vector<BRef> brefs;
+    auto add_blayer = [&](BLayer *L, int n_out, int K, auto m, const std::vector<float> &bias) {
+        L->K16 = (K + 15) / 16;
+        L->n_tiles = (n_out + 31) / 32;
+        L->n_out = n_out;
+        size_t w = bbuf.size();
+        pack_a_bf16(bbuf, n_out, K, m);
+        size_t b = buf.size();
+        if (!bias.empty()) pack_bias(buf, bias.data(), n_out);
+        brefs.push_back({L, w, b, !bias.empty()});
     };
     // SDF parameters: per layer W [out][in] then b
     const float *p = sdf_params;
@@ -500,6 +510,65 @@ int tsdfs_field_create(const tsdfs_field_desc *d, const float *sdf_params,
     while (buf.size() % 4) buf.push_back(0.0f);
     for (int j = 0; j < 3; ++j) P.brgb[j] = q[(size_t)3 * W + j];
 
+    // ---- BF16 plan (see BPlan)
+    BPlan &Q = F->bplan;
+    memset(&Q, 0, sizeof(Q));
+    Q.n_hidden = d->n_hidden;
+    Q.skip_at = d->skip_at;
+    Q.d_gamma = dg;
+    Q.width = W;
+    Q.n_feat = d->n_feat;
+    Q.col_hidden = d->col_hidden;
+    Q.kb = d->beta * 1.4426950408889634f;
+    Q.c1 = 0.6931471805599453f / d->beta;
+    Q.scale = d->scale;
+    Q.inv_scale = 1.0f / d->scale;
+    for (int a = 0; a < 3; ++a) Q.center[a] = d->center[a];
+    {
+        const double rs2 = 0.70710678118654752440;
+        const float *pp = sdf_params;
+        for (int l = 0; l < d->n_hidden; ++l) {
+            const float *Wl = pp, *bl = pp + (size_t)dout[l] * din[l];
+            const double sc = (l == d->skip_at) ? rs2 : 1.0;
+            const int ld = din[l];
+            add_blayer(&Q.fwd[l], dout[l], din[l],
+                       [=](int r, int k) { return (float)(Wl[(size_t)r * ld + k] * sc); },
+                       std::vector<float>(bl, bl + dout[l]));
+            add_blayer(&Q.bwd[l], din[l], dout[l],
+                       [=](int r, int k) { return (float)(Wl[(size_t)k * ld + r] * sc); },
+                       std::vector<float>());
+            pp += (size_t)dout[l] * din[l] + dout[l];
+        }
+        const int nf = d->n_feat;
+        std::vector<float> ob(nf + 1);
+        for (int r = 0; r < nf; ++r) ob[r] = bout[1 + r];
+        ob[nf] = bout[0];
+        add_blayer(&Q.feat, nf + 1, W,
+                   [=](int r, int k) { return r < nf ? Wout[(size_t)(1 + r) * W + k] : Wout[k]; },
+                   ob);
+        const float *cc = color_params;
+        for (int l = 0; l < d->col_hidden; ++l) {
+            const int K = l == 0 ? cin : W;
+            const float *Wl = cc;
+            std::vector<float> cb(cc + (size_t)W * K, cc + (size_t)W * K + W);
+            if (l == 0)   // input order [feat, x_hat, v, grad f]
+                add_blayer(&Q.col[l], W, K,
+                           [=](int r, int k) {
+                               return Wl[(size_t)r * K + (k < nf ? 9 + k : k - nf)];
+                           },
+                           cb);
+            else
+                add_blayer(&Q.col[l], W, K,
+                           [=](int r, int k) { return Wl[(size_t)r * K + k]; }, cb);
+            cc += (size_t)W * K + W;
+        }
+        std::vector<float> rb(cc + (size_t)3 * W, cc + (size_t)3 * W + 3);
+        add_blayer(&Q.rgb, 3, W, [=](int r, int k) { return cc[(size_t)r * W + k]; }, rb);
+    }
+    size_t bwf_off = buf.size();
+    buf.insert(buf.end(), Wout, Wout + W);
+    while (buf.size() % 4) buf.push_back(0.0f);
+
     size_t fbytes = buf.size() * sizeof(float);
     size_t bbytes = (bbuf.size() * sizeof(uint16_t) + 255) / 256 * 256;
     hipError_t e = hipMalloc((void **)&F->dev, fbytes + bbytes);
@@ -522,9 +591,25 @@ int tsdfs_field_create(const tsdfs_field_desc *d, const float *sdf_params,
     }
     for (auto &r : refs) {
         r.L->Wp = F->dev + r.w;
-        r.L->Wb = (const bf16x8 *)(devb + r.wb);
         r.L->b = r.has_b ? F->dev + r.b : nullptr;
     }
+    for (auto &r : brefs) {
+        r.L->W = (const bf16x8 *)(devb + r.w);
+        r.L->b = r.has_b ? F->dev + r.b : nullptr;
+    }
+    {
+        // the output layer as two views: feature tiles, then the f tile
+        BLayer full = Q.feat;
+        const int nft = F->desc.n_feat / 32;
+        Q.feat.n_tiles = nft;
+        Q.feat.n_out = F->desc.n_feat;
+        Q.fout = full;
+        Q.fout.W = full.W + (size_t)nft * full.K16 * 64;
+        Q.fout.b = full.b + (size_t)nft * 32;
+        Q.fout.n_tiles = 1;
+        Q.fout.n_out = 1;
+    }
+    Q.wf = F->dev + bwf_off;
     P.wf = F->dev + wf_off;
     P.wrgb = F->dev + wrgb_off;
     // plain parameter copies and layer offsets for the backward pass
@@ -607,7 +692,7 @@ int sdf_mlp_fwd(const tsdfs_field *F, const float *o, const float *v, const floa
     int64_t tiles = (s_cap + kTile - 1) / kTile;
     if (precision == TSDFS_BF16) {
         int grid = (int)(tiles < 2 * F->n_wg ? tiles : 2 * F->n_wg);
-        launch_field_bf16(F->plan, grid, o, v, t, ray_id, s_cap, s_count_dev, f, grad_f, rgb,
+        launch_field_bf16(F->bplan, grid, o, v, t, ray_id, s_cap, s_count_dev, f, grad_f, rgb,
                           (float *)ws, as_stream(stream));
     } else {
         int grid = (int)(tiles < F->n_wg ? tiles : F->n_wg);

@@ -19,12 +19,42 @@ constexpr int kScratchLayer = 8 * 4 * 16 * 64;  // floats per layer per workgrou
 
 struct Layer {
     const float *Wp;   // FP32 A operand, packed [n_tiles][K8/8][64][4]
-    const bf16x8 *Wb;  // BF16 A operand, packed [n_tiles][K16][64] (8 bf16 per lane)
     const float *b;    // bias [n_tiles*32] (zero padded), may be NULL
     int K8;            // K padded to a multiple of 8
-    int K16;           // K padded to a multiple of 16, in steps of 16
     int n_tiles;       // ceil(n_out / 32)
     int n_out;
+};
+
+// BF16 A operand of v_mfma_f32_32x32x16_bf16, packed [n_tiles][K16][64 lanes]
+// (8 bf16 per lane), with its FP32 bias.
+struct BLayer {
+    const bf16x8 *W;
+    const float *b;    // [n_tiles*32] zero padded, or NULL
+    int K16;           // K / 16, rounded up
+    int n_tiles;
+    int n_out;
+};
+
+// Network as the BF16 kernel runs it.  Differences from Plan: the 1/sqrt(2)
+// of the skip concatenation is folded into the weights of layer skip_at (and
+// its transpose); the output layer has the feature rows first and the f row
+// last (row n_feat, i.e. row 0 of tile n_feat/32); the colour network's first
+// layer takes its input as [feat, x_hat, v, grad f]; the rgb layer is a
+// 32-row tile with 3 live rows.
+struct BPlan {
+    int n_hidden, skip_at, d_gamma, width, n_feat, col_hidden;
+    float kb;          // beta * log2(e)
+    float c1;          // ln(2) / beta
+    float scale;
+    float inv_scale;
+    float center[3];
+    BLayer fwd[kMaxHidden];
+    BLayer feat;       // rows [0, n_feat) of the output layer
+    BLayer fout;       // tile holding the f row
+    BLayer bwd[kMaxHidden];
+    BLayer col[kMaxColor];
+    BLayer rgb;
+    const float *wf;   // f row of the output layer in FP32 [width]
 };
 
 struct Plan {
@@ -43,7 +73,7 @@ struct Plan {
 
 void release_blas(tsdfs_field *F);
 
-int launch_field_bf16(const Plan &P, int grid, const float *o, const float *v, const float *t,
+int launch_field_bf16(const BPlan &P, int grid, const float *o, const float *v, const float *t,
                       const int32_t *ray_id, int64_t s_cap, const int64_t *s_count, float *f,
                       float *g, float *rgb, float *ws, hipStream_t stream);
 
@@ -52,6 +82,7 @@ int launch_field_bf16(const Plan &P, int grid, const float *o, const float *v, c
 struct tsdfs_field {
     tsdfs_field_desc desc;
     tsdfs::Plan plan;
+    tsdfs::BPlan bplan;
     float *dev = nullptr;        // all packed weights (FP32 + BF16 blocks)
     int n_wg = 0;                // persistent grid size (compute units)
     // plain row-major FP32 parameters (host layout) for the backward pass
@@ -86,11 +117,5 @@ __device__ __forceinline__ int gamma_deriv(const float *xh, int j, float &d) {
     d = rem < 3 ? sc * cosf(x) : -sc * sinf(x);
     return a;
 }
-
-void release_blas(tsdfs_field *F);
-
-int launch_field_bf16(const Plan &P, int grid, const float *o, const float *v, const float *t,
-                      const int32_t *ray_id, int64_t s_cap, const int64_t *s_count, float *f,
-                      float *g, float *rgb, float *ws, hipStream_t stream);
 
 }  // namespace tsdfs
