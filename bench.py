@@ -80,6 +80,8 @@ def main():
     ap.add_argument("--cpu-rays", type=int, default=1024)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-hs", action="store_true")
+    ap.add_argument("--no-other", action="store_true", help="skip the other-precision leg")
+    ap.add_argument("--no-train", action="store_true", help="skip the training-step leg")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a device-to-device copy of MIB MiB (to scale HBM counters)")
     args = ap.parse_args()
@@ -218,31 +220,34 @@ def main():
 
     # ---- the other precision on the same step
     other = _lib.FP32 if prec == _lib.BF16 else _lib.BF16
-    oname = "f32" if other == _lib.FP32 else "bf16"
-    R.precision = other
-    for _ in range(args.warmup):
-        R.render(ro_d, rv_d)
-    ev_o = {}
-    torch.cuda.synchronize()
-    start.record()
-    for _ in range(args.steps):
-        R.render(ro_d, rv_d, events=ev_o)
-    end.record()
-    torch.cuda.synchronize()
-    R.precision = prec
-    ms_o = start.elapsed_time(end) / args.steps
-    field_o = float(np.mean([a.elapsed_time(b) for a, b in ev_o["field"]]))
-    ach_o = S * fl_sample / (field_o * 1e-3) / 1e12
-    result[oname] = {
-        "ms_per_step": ms_o, "rays_per_s": n_rays / (ms_o * 1e-3), "field_ms": field_o,
-        "roofline": {"kernel": "k_field_bf16" if other == _lib.BF16 else "k_field_fp32",
-                     "bound": "mfma", "achieved": ach_o, "peak": PEAK_TFLOPS[oname],
-                     "unit": "TFLOP/s", "frac": ach_o / PEAK_TFLOPS[oname]},
-    }
-    log(f"{oname}: {ms_o:.3f} ms/step")
+    if args.no_other:
+        other = None
+    if other is not None:
+        oname = "f32" if other == _lib.FP32 else "bf16"
+        R.precision = other
+        for _ in range(args.warmup):
+            R.render(ro_d, rv_d)
+        ev_o = {}
+        torch.cuda.synchronize()
+        start.record()
+        for _ in range(args.steps):
+            R.render(ro_d, rv_d, events=ev_o)
+        end.record()
+        torch.cuda.synchronize()
+        R.precision = prec
+        ms_o = start.elapsed_time(end) / args.steps
+        field_o = float(np.mean([a.elapsed_time(b) for a, b in ev_o["field"]]))
+        ach_o = S * fl_sample / (field_o * 1e-3) / 1e12
+        result[oname] = {
+            "ms_per_step": ms_o, "rays_per_s": n_rays / (ms_o * 1e-3), "field_ms": field_o,
+            "roofline": {"kernel": "k_field_bf16" if other == _lib.BF16 else "k_field_fp32",
+                         "bound": "mfma", "achieved": ach_o, "peak": PEAK_TFLOPS[oname],
+                         "unit": "TFLOP/s", "frac": ach_o / PEAK_TFLOPS[oname]},
+        }
+        log(f"{oname}: {ms_o:.3f} ms/step")
 
     # ---- one TSDF-bounded training step (8192 rays + 8192 eikonal points)
-    if cfg.name in ("c2", "c3", "c4"):
+    if cfg.name in ("c2", "c3", "c4") and not args.no_train:
         from paper_2311_17878_amd.autograd import train_step
         tro, trv, ttarget = cfg.training_batch(8192, seed=0)
         teik = cfg.eikonal_points(8192, seed=0)

@@ -534,8 +534,15 @@ int tsdfs_field_create(const tsdfs_field_desc *d, const float *sdf_params,
             add_blayer(&Q.fwd[l], dout[l], din[l],
                        [=](int r, int k) { return (float)(Wl[(size_t)r * ld + k] * sc); },
                        std::vector<float>(bl, bl + dout[l]));
+            // the transposes take 1/255 (softplus' is stored as 255 sigma)
+            // and, for the last hidden layer, diag(w_f): the reverse pass
+            // then starts from softplus' of that layer alone
+            const float *wfv = (l + 1 == d->n_hidden) ? Wout : nullptr;
             add_blayer(&Q.bwd[l], din[l], dout[l],
-                       [=](int r, int k) { return (float)(Wl[(size_t)k * ld + r] * sc); },
+                       [=](int r, int k) {
+                           return (float)(Wl[(size_t)k * ld + r] * sc / 255.0 *
+                                          (wfv ? (double)wfv[k] : 1.0));
+                       },
                        std::vector<float>());
             pp += (size_t)dout[l] * din[l] + dout[l];
         }
@@ -565,9 +572,6 @@ int tsdfs_field_create(const tsdfs_field_desc *d, const float *sdf_params,
         std::vector<float> rb(cc + (size_t)3 * W, cc + (size_t)3 * W + 3);
         add_blayer(&Q.rgb, 3, W, [=](int r, int k) { return cc[(size_t)r * W + k]; }, rb);
     }
-    size_t bwf_off = buf.size();
-    buf.insert(buf.end(), Wout, Wout + W);
-    while (buf.size() % 4) buf.push_back(0.0f);
 
     size_t fbytes = buf.size() * sizeof(float);
     size_t bbytes = (bbuf.size() * sizeof(uint16_t) + 255) / 256 * 256;
@@ -609,7 +613,6 @@ int tsdfs_field_create(const tsdfs_field_desc *d, const float *sdf_params,
         Q.fout.n_tiles = 1;
         Q.fout.n_out = 1;
     }
-    Q.wf = F->dev + bwf_off;
     P.wf = F->dev + wf_off;
     P.wrgb = F->dev + wrgb_off;
     // plain parameter copies and layer offsets for the backward pass

@@ -13,10 +13,12 @@
 // from LDS likewise, and the bias enters as the first MFMA's accumulator.
 // f and rgb come out of the same MFMA pipeline (the f row sits in its own
 // tile of the output layer; rgb is a 32-row tile with 3 live rows).
-// Softplus derivatives and the feature vector go to a per-workgroup global
-// scratch slot in BF16 (accumulator layout, 32 B per lane and column block);
-// the encoding, its derivative and the reverse-pass values on the encoding
-// rows stay FP32 in the same slot.
+// The softplus derivatives (sigma in [0, 1]) go to a per-workgroup global
+// scratch slot as 8-bit codes round(255 sigma) (absolute error <= 1/510, the
+// size of one BF16 rounding of sigma near 1; the 1/255 sits in the
+// transposed weights), the feature vector as BF16, both in accumulator
+// layout; the encoding, its derivative and the reverse-pass values on the
+// encoding rows stay FP32 in the same slot.
 #include "field_common.hpp"
 
 namespace tsdfs {
@@ -33,8 +35,6 @@ __device__ __forceinline__ uint32_t pk(float a, float b) {
     floatx2 f = {a, b};
     return __builtin_bit_cast(uint32_t, __builtin_convertvector(f, bf16x2));  // RNE
 }
-__device__ __forceinline__ float lo16(uint32_t u) { return __uint_as_float(u << 16); }
-__device__ __forceinline__ float hi16(uint32_t u) { return __uint_as_float(u & 0xffff0000u); }
 
 // Opaque copy of a per-lane element offset: addresses are rebuilt from the
 // kernel's base pointers where they are used, instead of being hoisted out
@@ -109,13 +109,13 @@ __device__ __forceinline__ void gemm_t(const BLayer &L, const __bf16 *act,
     if (NT == 2) ao[NT - 1] = (unsigned)opq(s.t1 * K16 * 64 + lane);
     const __bf16 *bp = act + (s.c0 * 32 + col) * kStride + khalf * 8;
     bf16x8 a0[NT], a1[NT], a2[NT], b0[NC], b1[NC], b2[NC];
-    auto load = [&](bf16x8 (&a)[NT], bf16x8 (&b)[NC], int k) {
+    auto load = [&](bf16x8 (&a)[NT], bf16x8 (&b)[NC], int k) __attribute__((always_inline)) {
 #pragma unroll
         for (int tt = 0; tt < NT; ++tt) a[tt] = W[ao[tt] + (unsigned)k * 64u];
 #pragma unroll
         for (int j = 0; j < NC; ++j) b[j] = *(const bf16x8 *)(bp + j * 32 * kStride + k * 16);
     };
-    auto mma = [&](const bf16x8 (&a)[NT], const bf16x8 (&b)[NC]) {
+    auto mma = [&](const bf16x8 (&a)[NT], const bf16x8 (&b)[NC]) __attribute__((always_inline)) {
 #pragma unroll
         for (int tt = 0; tt < NT; ++tt)
 #pragma unroll
@@ -157,49 +157,91 @@ __device__ __forceinline__ void gemm_t(const BLayer &L, const __bf16 *act,
     if (k + 1 < K16) mma(a2, b2);
 }
 
-template <int NT, int NC, class F>
-__device__ __forceinline__ void each(floatx16 (&acc)[NT][NC], const Split &s, F &f) {
+// One layer: this wave's share of the product; pre(t, c, buf) for each
+// 32x32 block of the share (loads the epilogue needs, issued before the
+// barrier so that their latency overlaps it); a workgroup barrier when the
+// epilogue overwrites the activations the product reads; then
+// epi(acc, t, c, buf) on each block.
+template <int NT, int NC, class Pre, class Epi>
+__device__ __forceinline__ void layer_t(const BLayer &L, const __bf16 *act, const Split &s,
+                                        int lane, bool sync, Pre &pre, Epi &epi) {
+    floatx16 acc[NT][NC];
+    gemm_t<NT, NC>(L, act, acc, s, lane);
+    uint4 buf[NT][NC][2];
 #pragma unroll
     for (int tt = 0; tt < NT; ++tt)
 #pragma unroll
-        for (int j = 0; j < NC; ++j) f(acc[tt][j], tt == 0 ? s.t0 : s.t1, s.c0 + j);
+        for (int j = 0; j < NC; ++j) pre(tt == 0 ? s.t0 : s.t1, s.c0 + j, buf[tt][j]);
+    if (sync) __syncthreads();
+#pragma unroll
+    for (int tt = 0; tt < NT; ++tt)
+#pragma unroll
+        for (int j = 0; j < NC; ++j) epi(acc[tt][j], tt == 0 ? s.t0 : s.t1, s.c0 + j, buf[tt][j]);
 }
 
-// One layer: this wave's share of the product, a workgroup barrier (when
-// the epilogue overwrites the activations the product reads), then
-// epi(acc, t, c) on each 32x32 block of the share.
-template <class F>
+template <class Pre, class Epi>
 __device__ __forceinline__ void run_layer(const BLayer &L, const __bf16 *act, int wave, int lane,
-                                          bool sync, F epi) {
+                                          bool sync, Pre pre, Epi epi) {
     const Split s = split_of(L.n_tiles, wave);
     if (s.t0 < 0) {
         if (sync) __syncthreads();
     } else if (s.nc == 4 && s.t1 >= 0) {
-        floatx16 acc[2][4];
-        gemm_t<2, 4>(L, act, acc, s, lane);
-        if (sync) __syncthreads();
-        each(acc, s, epi);
+        layer_t<2, 4>(L, act, s, lane, sync, pre, epi);
     } else if (s.nc == 4) {
-        floatx16 acc[1][4];
-        gemm_t<1, 4>(L, act, acc, s, lane);
-        if (sync) __syncthreads();
-        each(acc, s, epi);
+        layer_t<1, 4>(L, act, s, lane, sync, pre, epi);
     } else if (s.nc == 2) {
-        floatx16 acc[1][2];
-        gemm_t<1, 2>(L, act, acc, s, lane);
-        if (sync) __syncthreads();
-        each(acc, s, epi);
+        layer_t<1, 2>(L, act, s, lane, sync, pre, epi);
     } else {
-        floatx16 acc[1][1];
-        gemm_t<1, 1>(L, act, acc, s, lane);
-        if (sync) __syncthreads();
-        each(acc, s, epi);
+        layer_t<1, 1>(L, act, s, lane, sync, pre, epi);
     }
 }
 
-// Element offset (in uint4) of scratch block [slot][t][c][lane] (16 bf16).
-__device__ __forceinline__ int sbf(int slot, int t, int c, int lane) {
-    return ((((slot * 8 + t) * 4 + c) * 64 + lane) * 2);
+// ld(t, c, buf) for every block of the share, then use(t, c, buf): all the
+// loads are in flight together.
+template <int NT, int NC, class Ld, class Use>
+__device__ __forceinline__ void blocks_t(const Split &s, Ld &ld, Use &use) {
+    uint4 buf[NT][NC][2];
+#pragma unroll
+    for (int tt = 0; tt < NT; ++tt)
+#pragma unroll
+        for (int j = 0; j < NC; ++j) ld(tt == 0 ? s.t0 : s.t1, s.c0 + j, buf[tt][j]);
+#pragma unroll
+    for (int tt = 0; tt < NT; ++tt)
+#pragma unroll
+        for (int j = 0; j < NC; ++j) use(tt == 0 ? s.t0 : s.t1, s.c0 + j, buf[tt][j]);
+}
+
+template <class Ld, class Use>
+__device__ __forceinline__ void blocks(const Split &s, Ld ld, Use use) {
+    if (s.t0 < 0) return;
+    if (s.nc == 4 && s.t1 >= 0)
+        blocks_t<2, 4>(s, ld, use);
+    else if (s.nc == 4)
+        blocks_t<1, 4>(s, ld, use);
+    else if (s.nc == 2)
+        blocks_t<1, 2>(s, ld, use);
+    else
+        blocks_t<1, 1>(s, ld, use);
+}
+
+// Scratch offsets in uint4: softplus' codes [layer][tile][c][lane] (16
+// bytes), then the features [tile][c][lane] (16 bf16, two uint4).
+__device__ __forceinline__ int ssp(int l, int t, int c, int lane) {
+    return ((l * 8 + t) * 4 + c) * 64 + lane;
+}
+__device__ __forceinline__ int sft(int n_hidden, int t, int c, int lane) {
+    return n_hidden * 2048 + ((t * 4 + c) * 64 + lane) * 2;
+}
+
+// 8-bit code of softplus' (in [0, 1]): round(255 sigma), from 255 sigma.
+__device__ __forceinline__ uint32_t pk_u8(float a, float b, float c, float d) {
+    uint32_t r = __builtin_amdgcn_cvt_pk_u8_f32(a, 0, 0u);
+    r = __builtin_amdgcn_cvt_pk_u8_f32(b, 1, r);
+    r = __builtin_amdgcn_cvt_pk_u8_f32(c, 2, r);
+    return __builtin_amdgcn_cvt_pk_u8_f32(d, 3, r);
+}
+__device__ __forceinline__ float u8f(uint32_t w, int byte) {
+    return (float)((w >> (8 * byte)) & 0xffu);
 }
 
 // Store rows r0..r0+3 of sample cc (two packed bf16 pairs).
@@ -209,60 +251,98 @@ __device__ __forceinline__ void st4(__bf16 *act, int cc, int r0, uint32_t p01, u
 
 // Softplus_beta and its derivative from z: with a = beta log2(e) z,
 // L = log2(1 + 2^-|a|) and m = max(-a, 0) + L,
-//   h = softplus_beta(z) = z + m ln2 / beta,   sigma = d h / d z = 2^-m.
+//   h = softplus_beta(z) = z + m ln2 / beta,   sigma = d h / d z = 2^-m;
+// returned as h and 255 sigma (the scale of its 8-bit code).
 // For z < 0 the first form cancels z against -z; its absolute error stays
 // at the rounding level of z itself, far below the BF16 rounding of h.
-__device__ __forceinline__ void softplus2(float z, float kb, float c1, float &h, float &sp) {
+__device__ __forceinline__ void softplus2(float z, float kb, float c1, float &h, float &sp255) {
+    const float log2_255 = 7.99435343685885793f;
     float a = z * kb;
     float L = __builtin_amdgcn_logf(1.0f + __builtin_amdgcn_exp2f(-fabsf(a)));
     float m = fmaxf(-a, 0.0f) + L;
     h = fmaf(m, c1, z);
-    sp = __builtin_amdgcn_exp2f(-m);
+    sp255 = __builtin_amdgcn_exp2f(log2_255 - m);
 }
 
-// Encoding gamma_j(x_hat) and d gamma_j / d x_hat_a(j) for the tile's
-// samples, [j][sample] in FP32 scratch; one sincos per (frequency, axis).
-__device__ __forceinline__ void encode_tile(const float *s_xh, int d_gamma, float *gam,
-                                            float *jac) {
-    for (int idx = threadIdx.x; idx < d_gamma * kTile; idx += kBThreads) {
-        int j = idx / kTile, c = idx % kTile;
-        if (j < 3) {
-            gam[idx] = s_xh[j * kTile + c];
-            jac[idx] = 1.0f;
+// Encoding gamma(x_hat) = [x_hat, sin(2^k x_hat), cos(2^k x_hat)]_k and
+// d gamma_j / d x_hat_a(j), [j][sample] in FP32 scratch, and gamma as the
+// first layer's input rows of act (then zeros up to k_pad); one sincos per
+// (frequency, axis, sample).
+__device__ __forceinline__ void encode_tile(int tid, const float *s_xh, int pe, float *gam,
+                                            float *jac, __bf16 *act, int k_pad) {
+    for (int idx = tid; idx < 3 * (pe + 1) * kTile; idx += kBThreads) {
+        const int c = idx % kTile, ka = idx / kTile, a = ka % 3, k = ka / 3 - 1;
+        const float x = s_xh[a * kTile + c];
+        if (k < 0) {
+            gam[a * kTile + c] = x;
+            jac[a * kTile + c] = 1.0f;
+            act[c * kStride + a] = (__bf16)x;
             continue;
         }
-        int jj = j - 3, k = jj / 6, rem = jj % 6;
-        if (rem >= 3) continue;   // the cos row is written with its sin row
-        float sc = ldexpf(1.0f, k), sn, cs;
-        sincosf(sc * s_xh[rem * kTile + c], &sn, &cs);
-        gam[idx] = sn;
-        jac[idx] = sc * cs;
-        gam[idx + 3 * kTile] = cs;
-        jac[idx + 3 * kTile] = -sc * sn;
+        const float sc = ldexpf(1.0f, k);
+        float sn, cs;
+        sincosf(sc * x, &sn, &cs);
+        const int js = 3 + 6 * k + a, jc = js + 3;
+        gam[js * kTile + c] = sn;
+        jac[js * kTile + c] = sc * cs;
+        gam[jc * kTile + c] = cs;
+        jac[jc * kTile + c] = -sc * sn;
+        act[c * kStride + js] = (__bf16)sn;
+        act[c * kStride + jc] = (__bf16)cs;
+    }
+    const int d_gamma = 3 + 6 * pe, n = k_pad - d_gamma;
+    for (int idx = tid; idx < n * kTile; idx += kBThreads)
+        act[(idx / n) * kStride + d_gamma + idx % n] = (__bf16)0.0f;
+}
+
+// act rows [r0, r0 + d_gamma) <- gam (the re-injected encoding); each thread
+// keeps one sample and issues all its loads (clamped to valid rows) before
+// its stores.
+__device__ __forceinline__ void inject_gamma(int tid, __bf16 *act, int r0, int d_gamma,
+                                             const float *gam) {
+    constexpr int kRowsPerPass = kBThreads / kTile;   // 2
+    const int c = tid % kTile, j0 = tid / kTile;
+    const float *g = gam + c;
+    float x[kGammaRows / kRowsPerPass];
+#pragma unroll
+    for (int i = 0; i < kGammaRows / kRowsPerPass; ++i)
+        x[i] = g[min(j0 + kRowsPerPass * i, d_gamma - 1) * kTile];
+#pragma unroll
+    for (int i = 0; i < kGammaRows / kRowsPerPass; ++i) {
+        const int j = j0 + kRowsPerPass * i;
+        if (j < d_gamma) act[c * kStride + r0 + j] = (__bf16)x[i];
     }
 }
 
-__device__ __forceinline__ int gamma_axis(int j) { return j < 3 ? j : ((j - 3) % 6) % 3; }
-
-// s_g[a][c] += sum_j eg[j][c] * jac[j][c] over the rows j of axis a
-__device__ __forceinline__ void gamma_grad_reduce(const float *eg, const float *jac, int d_gamma,
-                                                  float *s_g) {
-    for (int idx = threadIdx.x; idx < 3 * kTile; idx += kBThreads) {
-        int a = idx / kTile, c = idx % kTile;
+// s_g[a][c] += sum over the encoding rows j of axis a of eg[j][c] * jac[j][c]
+__device__ __forceinline__ void gamma_grad_reduce(int tid, const float *eg, const float *jac,
+                                                  int pe, float *s_g) {
+    constexpr int kMaxPe = (kGammaRows - 3) / 6;   // 10
+    for (int idx = tid; idx < 3 * kTile; idx += kBThreads) {
+        const int a = idx / kTile, c = idx % kTile;
+        const int base = a * kTile + c;
+        float e[1 + 2 * kMaxPe], d[1 + 2 * kMaxPe];
+#pragma unroll
+        for (int i = 0; i < 1 + 2 * kMaxPe; ++i) {
+            // row a, then 3 + 6k + a (sin) and 6 + 6k + a (cos); rows past
+            // the encoding read row a again and are dropped
+            const bool live = i < 1 + 2 * pe;
+            const int j = (i == 0 || !live) ? 0 : 3 + 6 * ((i - 1) >> 1) + 3 * ((i - 1) & 1);
+            e[i] = eg[base + j * kTile];
+            d[i] = live ? jac[base + j * kTile] : 0.0f;
+        }
         float sum = 0.0f;
-        for (int j = 0; j < d_gamma; ++j)
-            if (gamma_axis(j) == a) sum = fmaf(eg[j * kTile + c], jac[j * kTile + c], sum);
+#pragma unroll
+        for (int i = 0; i < 1 + 2 * kMaxPe; ++i) sum = fmaf(e[i], d[i], sum);
         s_g[a * kTile + c] += sum;
     }
 }
 
-// act[c][r0 + j] = src[j][c] (or 0 when src is NULL) for j < r1 - r0
-__device__ __forceinline__ void fill_rows(__bf16 *act, int r0, int r1, const float *src) {
+// act rows [r0, r1) <- 0
+__device__ __forceinline__ void zero_rows(int tid, __bf16 *act, int r0, int r1) {
     const int n = r1 - r0;
-    for (int idx = threadIdx.x; idx < n * kTile; idx += kBThreads) {
-        int c = idx / n, j = idx % n;
-        act[c * kStride + r0 + j] = (__bf16)(src ? src[j * kTile + c] : 0.0f);
-    }
+    for (int idx = tid; idx < n * kTile; idx += kBThreads)
+        act[(idx / n) * kStride + r0 + idx % n] = (__bf16)0.0f;
 }
 
 template <bool FULL>
@@ -276,27 +356,32 @@ k_field_bf16(const BPlan P, const float *__restrict__ o, const float *__restrict
     __shared__ float s_v[3 * kTile];
     __shared__ float s_g[3 * kTile];
 
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int col = lane & 31, khalf = lane >> 5;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     int64_t S = s_cap;
     if (s_count) {
         int64_t c = *s_count;
         S = c < s_cap ? c : s_cap;
     }
     const int64_t n_tiles = (S + kTile - 1) / kTile;
-    // slot: BF16 [n_hidden + 1][8][4][64][16], then FP32 eg, gam, jac [64][128]
+    // slot: softplus' codes [n_hidden][8][4][64][16 B], features
+    // [8][4][64][32 B], then (at (n_hidden + 1) x 64 KiB) FP32 eg, gam, jac [64][128]
     float *slot = ws + (size_t)blockIdx.x * (P.n_hidden + 1) * kScratchLayer;
     uint4 *scr = (uint4 *)slot;
     float *eg = slot + (size_t)(P.n_hidden + 1) * (kScratchLayer / 2);
     float *gam = eg + kGammaRows * kTile;
     float *jac = gam + kGammaRows * kTile;
-    const int feat_slot = P.n_hidden;
     const float kb = P.kb, c1 = P.c1;
+    const int pe = (P.d_gamma - 3) / 6;
 
     for (int64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
+        // the thread index is re-derived opaquely per tile so that per-lane
+        // addresses are rebuilt where used instead of living (spilled) across
+        // the tile loop
+        const int tid = opq((int)threadIdx.x);
+        const int lane = tid & 63, col = lane & 31, khalf = lane >> 5;
         const int64_t s0 = tile * kTile;
-        if (threadIdx.x < kTile) {
-            int64_t s = s0 + threadIdx.x;
+        if (tid < kTile) {
+            int64_t s = s0 + tid;
             float xh[3] = {0.f, 0.f, 0.f}, vv[3] = {0.f, 0.f, 0.f};
             if (s < S) {
                 int64_t r = ray_id[s];
@@ -310,50 +395,45 @@ k_field_bf16(const BPlan P, const float *__restrict__ o, const float *__restrict
             }
 #pragma unroll
             for (int a = 0; a < 3; ++a) {
-                s_xh[a * kTile + threadIdx.x] = xh[a];
-                s_v[a * kTile + threadIdx.x] = vv[a];
-                s_g[a * kTile + threadIdx.x] = 0.0f;
+                s_xh[a * kTile + tid] = xh[a];
+                s_v[a * kTile + tid] = vv[a];
+                s_g[a * kTile + tid] = 0.0f;
             }
         }
         __syncthreads();
-        encode_tile(s_xh, P.d_gamma, gam, jac);
+        encode_tile(tid, s_xh, pe, gam, jac, act, P.fwd[0].K16 * 16);
         __syncthreads();
-        fill_rows(act, 0, P.d_gamma, gam);
-        fill_rows(act, P.d_gamma, P.fwd[0].K16 * 16, nullptr);
-        __syncthreads();
+        auto no_pre = [](int, int, uint4 (&)[2]) __attribute__((always_inline)) {};
         // ---- SDF hidden layers: h = softplus(z) -> act, softplus'(z) -> scratch
         for (int l = 0; l < P.n_hidden; ++l) {
-            run_layer(P.fwd[l], act, wave, lane, true, [&](floatx16 &a, int t, int c) {
+            run_layer(P.fwd[l], act, wave, lane, true, no_pre,
+                      [&](floatx16 &a, int t, int c, const uint4 (&)[2]) __attribute__((always_inline)) {
                 const int cc = c * 32 + col;
-                uint32_t spk[8];
+                uint32_t spk[4];
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
                     float h[4], d[4];
 #pragma unroll
                     for (int u = 0; u < 4; ++u) softplus2(a[4 * q + u], kb, c1, h[u], d[u]);
                     st4(act, cc, t * 32 + q * 8 + khalf * 4, pk(h[0], h[1]), pk(h[2], h[3]));
-                    spk[2 * q] = pk(d[0], d[1]);
-                    spk[2 * q + 1] = pk(d[2], d[3]);
+                    spk[q] = pk_u8(d[0], d[1], d[2], d[3]);
                 }
-                if (FULL) {
-                    uint4 *so = scr + opq(sbf(l, t, c, lane));
-                    so[0] = make_uint4(spk[0], spk[1], spk[2], spk[3]);
-                    so[1] = make_uint4(spk[4], spk[5], spk[6], spk[7]);
-                }
+                if (FULL) scr[opq(ssp(l, t, c, lane))] = make_uint4(spk[0], spk[1], spk[2], spk[3]);
             });
             if (l + 1 == P.skip_at) {
                 // rows past this layer's outputs: the re-injected encoding (its
                 // 1/sqrt(2) is in the next layer's weights), then zeros
                 __syncthreads();
                 const int r = P.fwd[l].n_out;
-                fill_rows(act, r, r + P.d_gamma, gam);
+                inject_gamma(tid, act, r, P.d_gamma, gam);
                 if (r + P.d_gamma < P.fwd[l + 1].K16 * 16)
-                    fill_rows(act, r + P.d_gamma, P.fwd[l + 1].K16 * 16, nullptr);
+                    zero_rows(tid, act, r + P.d_gamma, P.fwd[l + 1].K16 * 16);
             }
             __syncthreads();
         }
         // ---- output layer: the f tile, and the features -> scratch
-        run_layer(P.fout, act, wave, lane, false, [&](floatx16 &a, int t, int c) {
+        run_layer(P.fout, act, wave, lane, false, no_pre,
+                  [&](floatx16 &a, int t, int c, const uint4 (&)[2]) __attribute__((always_inline)) {
             if (khalf == 0) {
                 int64_t s = s0 + c * 32 + col;
                 if (s < S) f_out[s] = P.scale * a[0];
@@ -363,63 +443,66 @@ k_field_bf16(const BPlan P, const float *__restrict__ o, const float *__restrict
             __syncthreads();
             continue;
         }
-        run_layer(P.feat, act, wave, lane, false, [&](floatx16 &a, int t, int c) {
+        run_layer(P.feat, act, wave, lane, false, no_pre,
+                  [&](floatx16 &a, int t, int c, const uint4 (&)[2]) __attribute__((always_inline)) {
             uint32_t fk[8];
 #pragma unroll
             for (int q = 0; q < 8; ++q) fk[q] = pk(a[2 * q], a[2 * q + 1]);
-            uint4 *so = scr + opq(sbf(feat_slot, t, c, lane));
+            uint4 *so = scr + opq(sft(P.n_hidden, t, c, lane));
             so[0] = make_uint4(fk[0], fk[1], fk[2], fk[3]);
             so[1] = make_uint4(fk[4], fk[5], fk[6], fk[7]);
         });
+        // scratch block (accumulator layout) -> act rows of tile t
+        auto st_rows = [&](int t, int c, uint32_t p0, uint32_t p1, uint32_t p2, uint32_t p3,
+                           uint32_t p4, uint32_t p5, uint32_t p6, uint32_t p7)
+            __attribute__((always_inline)) {
+            const int cc = c * 32 + col, r0 = t * 32 + khalf * 4;
+            st4(act, cc, r0, p0, p1);
+            st4(act, cc, r0 + 8, p2, p3);
+            st4(act, cc, r0 + 16, p4, p5);
+            st4(act, cc, r0 + 24, p6, p7);
+        };
+        // ---- reverse pass: delta_{L-1} = softplus'(z_{L-1}) (w_f is in the
+        // next product's weights)
         __syncthreads();
-        // ---- reverse pass: delta_{L-1} = w_f * softplus'(z_{L-1})
-        {
-            const int l = P.n_hidden - 1;
-            const Split sp = split_of(P.fwd[l].n_tiles, wave);
-            for (int tt = 0; tt < 2 && sp.t0 >= 0; ++tt) {
-                if (tt == 1 && sp.t1 < 0) break;
-                const int t = tt == 0 ? sp.t0 : sp.t1;
-                const float4 *wp = (const float4 *)(P.wf + opq(t * 32 + khalf * 4));
-                float4 w4[4];
+        blocks(split_of(P.fwd[P.n_hidden - 1].n_tiles, wave),
+               [&](int t, int c, uint4 (&b)[2]) __attribute__((always_inline)) {
+                   b[0] = scr[opq(ssp(P.n_hidden - 1, t, c, lane))];
+               },
+               [&](int t, int c, uint4 (&b)[2]) __attribute__((always_inline)) {
+                   const uint32_t w[4] = {b[0].x, b[0].y, b[0].z, b[0].w};
+                   uint32_t p[8];
 #pragma unroll
-                for (int q = 0; q < 4; ++q) w4[q] = wp[2 * q];
-                for (int j = 0; j < sp.nc; ++j) {
-                    const int c = sp.c0 + j, cc = c * 32 + col;
-                    const uint4 *si = scr + opq(sbf(l, t, c, lane));
-                    uint4 p0 = si[0], p1 = si[1];
-                    uint32_t sk[8] = {p0.x, p0.y, p0.z, p0.w, p1.x, p1.y, p1.z, p1.w};
-#pragma unroll
-                    for (int q = 0; q < 4; ++q) {
-                        float d0 = lo16(sk[2 * q]) * w4[q].x, d1 = hi16(sk[2 * q]) * w4[q].y;
-                        float d2 = lo16(sk[2 * q + 1]) * w4[q].z, d3 = hi16(sk[2 * q + 1]) * w4[q].w;
-                        st4(act, cc, t * 32 + q * 8 + khalf * 4, pk(d0, d1), pk(d2, d3));
-                    }
-                }
-            }
-            __syncthreads();
-        }
+                   for (int q = 0; q < 4; ++q) {
+                       p[2 * q] = pk(u8f(w[q], 0), u8f(w[q], 1));
+                       p[2 * q + 1] = pk(u8f(w[q], 2), u8f(w[q], 3));
+                   }
+                   st_rows(t, c, p[0], p[1], p[2], p[3], p[4], p[5], p[6], p[7]);
+               });
+        __syncthreads();
         // e_{l-1} = W_l^T delta_l; delta_{l-1} = e * softplus'(z_{l-1}); the
         // rows of the re-injected encoding (skip layer) and of the first
         // layer's input hold d f / d gamma (FP32, eg), reduced into grad f.
         for (int l = P.n_hidden - 1; l >= 0; --l) {
             const int n_prev = l > 0 ? P.fwd[l - 1].n_out : 0;
             const int sp_tiles = l > 0 ? P.fwd[l - 1].n_tiles : 0;
-            run_layer(P.bwd[l], act, wave, lane, true, [&](floatx16 &a, int t, int c) {
+            run_layer(P.bwd[l], act, wave, lane, true,
+                      [&](int t, int c, uint4 (&b)[2]) __attribute__((always_inline)) {
+                          // rows of tiles past the previous layer's outputs
+                          // take softplus' = 0 (the load stays in bounds)
+                          const bool live = t < sp_tiles;
+                          const uint4 p0 = scr[opq(ssp(l > 0 ? l - 1 : 0, live ? t : 0, c, lane))];
+                          b[0] = live ? p0 : make_uint4(0, 0, 0, 0);
+                      },
+                      [&](floatx16 &a, int t, int c, const uint4 (&b)[2]) __attribute__((always_inline)) {
                 const int cc = c * 32 + col;
-                uint32_t sk[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-                if (t < sp_tiles) {
-                    const uint4 *si = scr + opq(sbf(l - 1, t, c, lane));
-                    uint4 p0 = si[0], p1 = si[1];
-                    sk[0] = p0.x; sk[1] = p0.y; sk[2] = p0.z; sk[3] = p0.w;
-                    sk[4] = p1.x; sk[5] = p1.y; sk[6] = p1.z; sk[7] = p1.w;
-                }
+                const uint32_t sk[4] = {b[0].x, b[0].y, b[0].z, b[0].w};
                 const bool plain = (t + 1) * 32 <= n_prev;   // no encoding rows
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
                     const int r0 = t * 32 + q * 8 + khalf * 4;
-                    float e[4] = {a[4 * q] * lo16(sk[2 * q]), a[4 * q + 1] * hi16(sk[2 * q]),
-                                  a[4 * q + 2] * lo16(sk[2 * q + 1]),
-                                  a[4 * q + 3] * hi16(sk[2 * q + 1])};
+                    float e[4] = {a[4 * q] * u8f(sk[q], 0), a[4 * q + 1] * u8f(sk[q], 1),
+                                  a[4 * q + 2] * u8f(sk[q], 2), a[4 * q + 3] * u8f(sk[q], 3)};
                     if (!plain) {
 #pragma unroll
                         for (int u = 0; u < 4; ++u) {
@@ -434,47 +517,39 @@ k_field_bf16(const BPlan P, const float *__restrict__ o, const float *__restrict
             });
             __syncthreads();
             if (l == P.skip_at || l == 0) {
-                gamma_grad_reduce(eg, jac, P.d_gamma, s_g);
+                gamma_grad_reduce(tid, eg, jac, pe, s_g);
                 __syncthreads();
             }
         }
         // ---- grad f out; colour input [feat, x_hat, v, grad f]
-        if (threadIdx.x < kTile) {
-            int64_t s = s0 + threadIdx.x;
+        if (tid < kTile) {
+            int64_t s = s0 + tid;
             if (s < S) {
 #pragma unroll
-                for (int a = 0; a < 3; ++a) g_out[3 * s + a] = s_g[a * kTile + threadIdx.x];
+                for (int a = 0; a < 3; ++a) g_out[3 * s + a] = s_g[a * kTile + tid];
             }
         }
-        {
-            const Split sp = split_of(P.feat.n_tiles, wave);
-            for (int tt = 0; tt < 2 && sp.t0 >= 0; ++tt) {
-                if (tt == 1 && sp.t1 < 0) break;
-                const int t = tt == 0 ? sp.t0 : sp.t1;
-                for (int j = 0; j < sp.nc; ++j) {
-                    const int c = sp.c0 + j, cc = c * 32 + col;
-                    const uint4 *si = scr + opq(sbf(feat_slot, t, c, lane));
-                    uint4 p0 = si[0], p1 = si[1];
-                    const int r0 = t * 32 + khalf * 4;
-                    st4(act, cc, r0, p0.x, p0.y);
-                    st4(act, cc, r0 + 8, p0.z, p0.w);
-                    st4(act, cc, r0 + 16, p1.x, p1.y);
-                    st4(act, cc, r0 + 24, p1.z, p1.w);
-                }
-            }
-        }
-        for (int idx = threadIdx.x; idx < 9 * kTile; idx += kBThreads) {
+        blocks(split_of(P.feat.n_tiles, wave),
+               [&](int t, int c, uint4 (&b)[2]) __attribute__((always_inline)) {
+                   const uint4 *si = scr + opq(sft(P.n_hidden, t, c, lane));
+                   b[0] = si[0];
+                   b[1] = si[1];
+               },
+               [&](int t, int c, uint4 (&b)[2]) __attribute__((always_inline)) {
+                   st_rows(t, c, b[0].x, b[0].y, b[0].z, b[0].w, b[1].x, b[1].y, b[1].z, b[1].w);
+               });
+        for (int idx = tid; idx < 9 * kTile; idx += kBThreads) {
             int c = idx / 9, j = idx % 9;
             float x = j < 3 ? s_xh[j * kTile + c]
                             : (j < 6 ? s_v[(j - 3) * kTile + c] : s_g[(j - 6) * kTile + c]);
             act[c * kStride + P.n_feat + j] = (__bf16)x;
         }
-        if (P.n_feat + 9 < P.col[0].K16 * 16)
-            fill_rows(act, P.n_feat + 9, P.col[0].K16 * 16, nullptr);
+        if (P.n_feat + 9 < P.col[0].K16 * 16) zero_rows(tid, act, P.n_feat + 9, P.col[0].K16 * 16);
         __syncthreads();
         // ---- colour hidden layers (ReLU)
         for (int l = 0; l < P.col_hidden; ++l) {
-            run_layer(P.col[l], act, wave, lane, true, [&](floatx16 &a, int t, int c) {
+            run_layer(P.col[l], act, wave, lane, true, no_pre,
+                      [&](floatx16 &a, int t, int c, const uint4 (&)[2]) __attribute__((always_inline)) {
                 const int cc = c * 32 + col;
 #pragma unroll
                 for (int q = 0; q < 4; ++q)
@@ -485,7 +560,8 @@ k_field_bf16(const BPlan P, const float *__restrict__ o, const float *__restrict
             __syncthreads();
         }
         // ---- rgb = sigmoid(W h + b): rows 0..2 of one tile, lanes 0..31
-        run_layer(P.rgb, act, wave, lane, false, [&](floatx16 &a, int t, int c) {
+        run_layer(P.rgb, act, wave, lane, false, no_pre,
+                  [&](floatx16 &a, int t, int c, const uint4 (&)[2]) __attribute__((always_inline)) {
             if (khalf == 0) {
                 int64_t s = s0 + c * 32 + col;
                 if (s < S) {

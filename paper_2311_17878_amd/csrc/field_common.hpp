@@ -38,7 +38,9 @@ struct BLayer {
 // Network as the BF16 kernel runs it.  Differences from Plan: the 1/sqrt(2)
 // of the skip concatenation is folded into the weights of layer skip_at (and
 // its transpose); the output layer has the feature rows first and the f row
-// last (row n_feat, i.e. row 0 of tile n_feat/32); the colour network's first
+// last (row n_feat, i.e. row 0 of tile n_feat/32); the transposes carry the
+// 1/255 of the 8-bit softplus' codes, and that of the last hidden layer
+// also diag(w_f) on its input side; the colour network's first
 // layer takes its input as [feat, x_hat, v, grad f]; the rgb layer is a
 // 32-row tile with 3 live rows.
 struct BPlan {
@@ -54,7 +56,6 @@ struct BPlan {
     BLayer bwd[kMaxHidden];
     BLayer col[kMaxColor];
     BLayer rgb;
-    const float *wf;   // f row of the output layer in FP32 [width]
 };
 
 struct Plan {
