@@ -26,7 +26,6 @@ namespace tsdfs {
 constexpr int kBWaves = 4;
 constexpr int kBThreads = kBWaves * 64;
 constexpr int kStride = 280;                  // bf16 elements per sample row in LDS
-constexpr int kGammaRows = 64;                // >= encoding width (39)
 
 typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
 typedef float floatx2 __attribute__((ext_vector_type(2)));
@@ -34,14 +33,6 @@ typedef float floatx2 __attribute__((ext_vector_type(2)));
 __device__ __forceinline__ uint32_t pk(float a, float b) {
     floatx2 f = {a, b};
     return __builtin_bit_cast(uint32_t, __builtin_convertvector(f, bf16x2));  // RNE
-}
-
-// Opaque copy of a per-lane element offset: addresses are rebuilt from the
-// kernel's base pointers where they are used, instead of being hoisted out
-// of the layer loops (and spilled) as 64-bit values.
-__device__ __forceinline__ int opq(int x) {
-    asm volatile("" : "+v"(x));
-    return x;
 }
 
 // Share of one layer's output for one wave: row tiles t0 (and t1 >= 0),
@@ -365,7 +356,7 @@ k_field_bf16(const BPlan P, const float *__restrict__ o, const float *__restrict
     const int64_t n_tiles = (S + kTile - 1) / kTile;
     // slot: softplus' codes [n_hidden][8][4][64][16 B], features
     // [8][4][64][32 B], then (at (n_hidden + 1) x 64 KiB) FP32 eg, gam, jac [64][128]
-    float *slot = ws + (size_t)blockIdx.x * (P.n_hidden + 1) * kScratchLayer;
+    float *slot = ws + (size_t)blockIdx.x * slot_floats(P.n_hidden);
     uint4 *scr = (uint4 *)slot;
     float *eg = slot + (size_t)(P.n_hidden + 1) * (kScratchLayer / 2);
     float *gam = eg + kGammaRows * kTile;
