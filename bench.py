@@ -252,21 +252,24 @@ def main():
         tro, trv, ttarget = cfg.training_batch(8192, seed=0)
         teik = cfg.eikonal_points(8192, seed=0)
         tro, trv, ttarget, teik = dev(tro), dev(trv), dev(ttarget), dev(teik)
-        out_t = train_step(R, tro, trv, ttarget, teik)   # warm-up (rocBLAS set-up)
-        torch.cuda.synchronize()
         n_t = max(1, min(args.steps, 5))
-        start.record()
-        for _ in range(n_t):
-            out_t = train_step(R, tro, trv, ttarget, teik)
-        end.record()
-        torch.cuda.synchronize()
-        tms = start.elapsed_time(end) / n_t
-        result["train_step"] = {
-            "rays": 8192, "eikonal_points": 8192, "samples": int(out_t[4]), "ms_per_step": tms,
-            "loss_rgb": float(out_t[0].item()), "loss_eik": float(out_t[1].item()),
-            "precision": "f32 (forward and backward)",
-        }
-        log(f"train step: {tms:.2f} ms")
+        for tname, tprec in (("train_step", _lib.FP32), ("train_step_bf16", _lib.BF16)):
+            out_t = train_step(R, tro, trv, ttarget, teik, precision=tprec)   # warm-up
+            torch.cuda.synchronize()
+            start.record()
+            for _ in range(n_t):
+                out_t = train_step(R, tro, trv, ttarget, teik, precision=tprec)
+            end.record()
+            torch.cuda.synchronize()
+            tms = start.elapsed_time(end) / n_t
+            result[tname] = {
+                "rays": 8192, "eikonal_points": 8192, "samples": int(out_t[4]), "ms_per_step": tms,
+                "rays_per_s": 8192 / (tms * 1e-3),
+                "loss_rgb": float(out_t[0].item()), "loss_eik": float(out_t[1].item()),
+                "precision": "f32 (forward and backward)" if tprec == _lib.FP32 else
+                             "bf16 product inputs, f32 accumulation (forward and backward)",
+            }
+            log(f"{tname}: {tms:.2f} ms")
 
     if not args.no_hs:
         for _ in range(1):

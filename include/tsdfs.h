@@ -238,8 +238,11 @@ int composite(const int32_t *offsets, int64_t n_rays, const float *v, const floa
  * second-order terms through grad f (colour input, opacity, eikonal).
  * Activations are recomputed inside the call (none are kept from
  * sdf_mlp_fwd).  d_f, d_grad_f may be NULL (zero).  eik_loss (optional,
- * device float) receives the eikonal term.  FP32 only.  The products run in
- * rocBLAS, which may allocate its own small workspace on first use.
+ * device float) receives the eikonal term.  precision: TSDFS_FP32, or
+ * TSDFS_BF16 (every matrix product takes BF16-rounded inputs with FP32
+ * accumulation; elementwise work, bias sums and outputs stay FP32).  The
+ * products run in rocBLAS, which may allocate its own small workspace on
+ * first use.
  * ws: sdf_mlp_bwd_ws_bytes(n_samples + n_eik). */
 int composite_bwd(const int32_t *offsets, int64_t n_rays, const float *v, const float *dt,
                   const float *f, const float *grad_f, const float *rgb, float s,

@@ -17,12 +17,14 @@ class FieldFn(torch.autograd.Function):
     """(f, grad f, rgb) at p = o[ray_id] + t v[ray_id] as a function of the
     network weights.  `sdf_w`, `col_w` are the device leaves holding the
     parameters the field was created from; their gradients come from
-    sdf_mlp_bwd (FP32), including the second-order terms through grad f."""
+    sdf_mlp_bwd (same precision as the forward), including the second-order
+    terms through grad f."""
 
     @staticmethod
     def forward(ctx, sdf_w, col_w, field, o, v, t, ray_id, precision=FP32):
         f, g, rgb = field.forward(o, v, t, ray_id, precision=precision)
         ctx.field = field
+        ctx.precision = precision
         ctx.save_for_backward(o, v, t, ray_id)
         return f, g, rgb
 
@@ -34,7 +36,8 @@ class FieldFn(torch.autograd.Function):
         d_f = d_f.contiguous() if d_f is not None else torch.zeros(S, device=dev)
         d_g = d_g.contiguous() if d_g is not None else torch.zeros((S, 3), device=dev)
         d_rgb = d_rgb.contiguous() if d_rgb is not None else torch.zeros((S, 3), device=dev)
-        d_sdf, d_col, _ = ctx.field.backward(o, v, t, ray_id, d_f, d_g, d_rgb)
+        d_sdf, d_col, _ = ctx.field.backward(o, v, t, ray_id, d_f, d_g, d_rgb,
+                                             precision=ctx.precision)
         return d_sdf, d_col, None, None, None, None, None, None
 
 
@@ -55,18 +58,20 @@ class CompositeFn(torch.autograd.Function):
         return d_f, d_g, d_c, None, None, None, None, None
 
 
-def train_step(renderer, o, v, target, eik_x, eik_lambda=0.1):
+def train_step(renderer, o, v, target, eik_x, eik_lambda=0.1, precision=FP32):
     """One TSDF-bounded training step on a batch of rays (C ABI only):
     Alg. 1 bounds -> placement -> field -> compositing -> photometric loss,
     then the compositing adjoint and the network backward with the eikonal
-    term on eik_x.  Returns (loss_rgb, loss_eik, d_sdf, d_col, n_samples)."""
+    term on eik_x.  precision selects FP32 or BF16-input products for the
+    field forward and the network backward.  Returns (loss_rgb, loss_eik,
+    d_sdf, d_col, n_samples)."""
     R = renderer
     b = ops.ray_bounds(R.grid, R.flags, o, v, R.t_far)
     p = ops.place(b, R.rho[0], R.rho[1], R.n_min, R.n_max, sync=True)
-    f, g, rgb = R.field.forward(o, v, p["t"], p["ray_id"], precision=FP32)
+    f, g, rgb = R.field.forward(o, v, p["t"], p["ray_id"], precision=precision)
     out = ops.composite(p["offsets"], v, p["t"], p["dt"], f, g, rgb, R.s)
     loss, d_out = ops.rgb_loss(out["rgb"], target)
     d_f, d_g, d_c = ops.composite_bwd(p["offsets"], v, p["dt"], f, g, rgb, R.s, d_out)
     d_sdf, d_col, eik = R.field.backward(o, v, p["t"], p["ray_id"], d_f, d_g, d_c,
-                                         eik_x=eik_x, eik_lambda=eik_lambda)
+                                         eik_x=eik_x, eik_lambda=eik_lambda, precision=precision)
     return loss, eik, d_sdf, d_col, p["S"]

@@ -4,7 +4,8 @@
 //
 // The network backward is organised layer by layer over all rows (samples
 // and eikonal points) with the activations recomputed inside the call:
-// plain row-major products go to rocBLAS (FP32), everything elementwise
+// plain row-major products go to rocBLAS (FP32, or BF16 inputs with FP32
+// accumulation; the bias sums stay FP32), everything elementwise
 // (softplus and its first two derivatives, the encoding Jacobian, masks,
 // the adjoint bookkeeping) runs in the kernels below.
 #include <rocblas/rocblas.h>
@@ -43,14 +44,40 @@ void release_blas(tsdfs_field *F) {
     }
 }
 
+// Product context: FP32 (rocBLAS SGEMM) or BF16 inputs with FP32
+// accumulation (each input rounded to BF16 into a scratch copy, then
+// rocBLAS gemm_ex with FP32 compute and output).
+struct Gemm {
+    rocblas_handle h;
+    hipStream_t st;
+    bool bf16;
+    __bf16 *sa, *sb;    // BF16 copies of the two inputs
+    size_t cap;         // elements per copy
+};
+
+// dst[i] = bf16(src[i]) (round to nearest even), n elements
+static void to_bf16_dev(hipStream_t st, const float *src, __bf16 *dst, int64_t n) {
+    map(n, st, [=] __device__(int64_t i) { dst[i] = (__bf16)src[i]; });
+}
+
 // Row-major C[M,N] = alpha op(A) op(B) + beta C (op(A): [M,K], op(B): [K,N]).
-static rocblas_status gemm_rm(rocblas_handle h, bool ta, bool tb, int M, int N, int K, float alpha,
+static rocblas_status gemm_rm(const Gemm &g, bool ta, bool tb, int M, int N, int K, float alpha,
                               const float *A, int lda, const float *B, int ldb, float beta, float *C,
                               int ldc) {
     if (M == 0 || N == 0) return rocblas_status_success;
-    return rocblas_sgemm(h, tb ? rocblas_operation_transpose : rocblas_operation_none,
-                         ta ? rocblas_operation_transpose : rocblas_operation_none, N, M, K, &alpha,
-                         B, ldb, A, lda, &beta, C, ldc);
+    const rocblas_operation oa = ta ? rocblas_operation_transpose : rocblas_operation_none;
+    const rocblas_operation ob = tb ? rocblas_operation_transpose : rocblas_operation_none;
+    if (!g.bf16)
+        return rocblas_sgemm(g.h, ob, oa, N, M, K, &alpha, B, ldb, A, lda, &beta, C, ldc);
+    // stored extents of the row-major inputs
+    const size_t na = (size_t)(ta ? K : M) * lda, nb = (size_t)(tb ? N : K) * ldb;
+    if (na > g.cap || nb > g.cap) return rocblas_status_invalid_size;
+    to_bf16_dev(g.st, A, g.sa, (int64_t)na);
+    to_bf16_dev(g.st, B, g.sb, (int64_t)nb);
+    return rocblas_gemm_ex(g.h, ob, oa, N, M, K, &alpha, g.sb, rocblas_datatype_bf16_r, ldb, g.sa,
+                           rocblas_datatype_bf16_r, lda, &beta, C, rocblas_datatype_f32_r, ldc, C,
+                           rocblas_datatype_f32_r, ldc, rocblas_datatype_f32_r,
+                           rocblas_gemm_algo_standard, 0, 0);
 }
 
 // y[N] += sum over rows of row-major A[R,N] (ld)
@@ -159,6 +186,8 @@ struct BwdBufs {
     float *Z2[kMaxHidden];                 // second-order contributions
     float *ones;                           // [R]
     float *loss;                           // [2] eikonal loss (device)
+    __bf16 *ca, *cb;                       // BF16 copies of product inputs [bf16_cap]
+    size_t bf16_cap;
 };
 
 static size_t carve(BwdBufs &b, const tsdfs_field *F, int R, char *base) {
@@ -206,6 +235,10 @@ static size_t carve(BwdBufs &b, const tsdfs_field *F, int R, char *base) {
     b.T3 = take((size_t)R * wide);
     b.ones = take((size_t)R);
     b.loss = take(2);
+    // every product input is an [R or <= 272 rows][<= 272] row-major block
+    b.bf16_cap = (size_t)(R > kMaxRows ? R : kMaxRows) * (kMaxRows + 8);
+    b.ca = (__bf16 *)take((b.bf16_cap + 1) / 2);
+    b.cb = (__bf16 *)take((b.bf16_cap + 1) / 2);
     return off;
 }
 
@@ -222,7 +255,7 @@ static int network_backward(tsdfs_field *F, const float *o, const float *v, cons
                             const int32_t *ray_id, int64_t S, const float *eik_x, int64_t P,
                             float eik_lambda, const float *d_f, const float *d_grad,
                             const float *d_rgb, float *gs, float *gc, char *ws, hipStream_t st,
-                            float *eik_loss_out) {
+                            float *eik_loss_out, bool bf16) {
     if (!F->blas) {
         rocblas_handle h;
         if (rocblas_create_handle(&h) != rocblas_status_success) {
@@ -239,6 +272,7 @@ static int network_backward(tsdfs_field *F, const float *o, const float *v, cons
     carve(B, F, R, ws);
     B.S = (int)S;
     B.P = (int)P;
+    const Gemm G{h, st, bf16, B.ca, B.cb, B.bf16_cap};
     const tsdfs_field_desc &d = F->desc;
     const Plan &PL = F->plan;
     const int W = d.width, nh = d.n_hidden, dg = B.dg, cin = B.cin, nf = d.n_feat;
@@ -296,7 +330,7 @@ static int network_backward(tsdfs_field *F, const float *o, const float *v, cons
     // ---- SDF forward
     for (int l = 0; l < nh; ++l) {
         const int in = F->din[l], out = F->dout[l];
-        BLAS(gemm_rm(h, false, true, R, out, in, 1.0f, B.X[l], in, Wl(l), in, 0.0f, B.Z[l], W));
+        BLAS(gemm_rm(G, false, true, R, out, in, 1.0f, B.X[l], in, Wl(l), in, 0.0f, B.Z[l], W));
         float *Z = B.Z[l], *Xn = B.X[l + 1];
         const float *bb = bl(l);
         const bool to_skip = (l + 1 == skip);
@@ -319,7 +353,7 @@ static int network_backward(tsdfs_field *F, const float *o, const float *v, cons
     }
     // output layer Y = X_last W_out^T + b_out
     const int ny = 1 + nf;
-    BLAS(gemm_rm(h, false, true, R, ny, W, 1.0f, B.X[nh], W, Wl(nh), W, 0.0f, B.Y, ny));
+    BLAS(gemm_rm(G, false, true, R, ny, W, 1.0f, B.X[nh], W, Wl(nh), W, 0.0f, B.Y, ny));
     {
         float *Y = B.Y;
         const float *bb = bl(nh);
@@ -337,7 +371,7 @@ static int network_backward(tsdfs_field *F, const float *o, const float *v, cons
     for (int l = nh - 1; l >= 1; --l) {
         const int in = F->din[l], out = F->dout[l];
         // E' = delta_l W_l : [R, in]
-        BLAS(gemm_rm(h, false, false, R, in, out, 1.0f, B.D[l], W, Wl(l), in, 0.0f, B.T0, W));
+        BLAS(gemm_rm(G, false, false, R, in, out, 1.0f, B.D[l], W, Wl(l), in, 0.0f, B.T0, W));
         const int np = F->dout[l - 1];
         const bool sk = (l == skip);
         float *E = B.E[l - 1], *Dm = B.D[l - 1], *Eg4 = B.Eg4, *T0 = B.T0;
@@ -356,7 +390,7 @@ static int network_backward(tsdfs_field *F, const float *o, const float *v, cons
         });
     }
     // encoding rows from layer 0: Eg0 = delta_0 W_0 : [R, dg]
-    BLAS(gemm_rm(h, false, false, R, dg, F->dout[0], 1.0f, B.D[0], W, Wl(0), dg, 0.0f, B.Eg0, dg));
+    BLAS(gemm_rm(G, false, false, R, dg, F->dout[0], 1.0f, B.D[0], W, Wl(0), dg, 0.0f, B.Eg0, dg));
     {
         float *g = B.g;
         const float *J = B.J, *Eg0 = B.Eg0, *Eg4 = B.Eg4;
@@ -389,7 +423,7 @@ static int network_backward(tsdfs_field *F, const float *o, const float *v, cons
     for (int l = 0; l < nc; ++l) {
         const int in = F->cdin[l];
         const float *X = l == 0 ? B.Cin : B.Hc[l - 1];
-        BLAS(gemm_rm(h, false, true, R, W, in, 1.0f, X, in, Wc + F->cw_off[l], in, 0.0f, B.Zc[l], W));
+        BLAS(gemm_rm(G, false, true, R, W, in, 1.0f, X, in, Wc + F->cw_off[l], in, 0.0f, B.Zc[l], W));
         float *Z = B.Zc[l], *H = B.Hc[l];
         const float *bb = Wc + F->cb_off[l];
         map((int64_t)R * W, st, [=] __device__(int64_t i) {
@@ -398,7 +432,7 @@ static int network_backward(tsdfs_field *F, const float *o, const float *v, cons
             H[i] = fmaxf(z, 0.0f);
         });
     }
-    BLAS(gemm_rm(h, false, true, R, 3, W, 1.0f, B.Hc[nc - 1], W, Wc + F->cw_off[nc], W, 0.0f, B.zo, 3));
+    BLAS(gemm_rm(G, false, true, R, 3, W, 1.0f, B.Hc[nc - 1], W, Wc + F->cw_off[nc], W, 0.0f, B.zo, 3));
     // ---- colour backward: dz_out = d rgb * rgb (1 - rgb)
     {
         float *zo = B.zo, *rgb = B.rgb, *dz = B.T0;
@@ -412,19 +446,19 @@ static int network_backward(tsdfs_field *F, const float *o, const float *v, cons
         });
     }
     // dW_c4 += dz^T H3 ; db += sum dz ; dH3 = dz W_c4
-    BLAS(gemm_rm(h, true, false, 3, W, R, 1.0f, B.T0, 3, B.Hc[nc - 1], W, 1.0f, gc + F->cw_off[nc], W));
+    BLAS(gemm_rm(G, true, false, 3, W, R, 1.0f, B.T0, 3, B.Hc[nc - 1], W, 1.0f, gc + F->cw_off[nc], W));
     BLAS(colsum(h, R, 3, B.T0, 3, B.ones, gc + F->cb_off[nc]));
-    BLAS(gemm_rm(h, false, false, R, W, 3, 1.0f, B.T0, 3, Wc + F->cw_off[nc], W, 0.0f, B.T1, W));
+    BLAS(gemm_rm(G, false, false, R, W, 3, 1.0f, B.T0, 3, Wc + F->cw_off[nc], W, 0.0f, B.T1, W));
     for (int l = nc - 1; l >= 0; --l) {
         const int in = F->cdin[l];
         float *dH = B.T1, *dZ = B.T2;
         const float *Z = B.Zc[l];
         map((int64_t)R * W, st, [=] __device__(int64_t i) { dZ[i] = Z[i] > 0.0f ? dH[i] : 0.0f; });
         const float *X = l == 0 ? B.Cin : B.Hc[l - 1];
-        BLAS(gemm_rm(h, true, false, W, in, R, 1.0f, dZ, W, X, in, 1.0f, gc + F->cw_off[l], in));
+        BLAS(gemm_rm(G, true, false, W, in, R, 1.0f, dZ, W, X, in, 1.0f, gc + F->cw_off[l], in));
         BLAS(colsum(h, R, W, dZ, W, B.ones, gc + F->cb_off[l]));
         // dX = dZ W_c : [R, in] (into T1, ld = in)
-        BLAS(gemm_rm(h, false, false, R, in, W, 1.0f, dZ, W, Wc + F->cw_off[l], in, 0.0f, B.T1, in));
+        BLAS(gemm_rm(G, false, false, R, in, W, 1.0f, dZ, W, Wc + F->cw_off[l], in, 0.0f, B.T1, in));
     }
     // B.T1 now holds d Cin [R, cin]
     // ---- g_bar = d grad (samples) + d Cin[:, 6:9] ; eikonal rows; encoding-space g_bar
@@ -465,8 +499,8 @@ static int network_backward(tsdfs_field *F, const float *o, const float *v, cons
     }
     // ---- second-order pass (adjoint of the reverse pass), forward in l
     // delta_bar_0 = gbar_g W_0^T ; dW_0 += delta_0^T gbar_g
-    BLAS(gemm_rm(h, false, true, R, F->dout[0], dg, 1.0f, B.gbar_g, dg, Wl(0), dg, 0.0f, B.T0, W));
-    BLAS(gemm_rm(h, true, false, F->dout[0], dg, R, 1.0f, B.D[0], W, B.gbar_g, dg, 1.0f, gW(0), dg));
+    BLAS(gemm_rm(G, false, true, R, F->dout[0], dg, 1.0f, B.gbar_g, dg, Wl(0), dg, 0.0f, B.T0, W));
+    BLAS(gemm_rm(G, true, false, F->dout[0], dg, R, 1.0f, B.D[0], W, B.gbar_g, dg, 1.0f, gW(0), dg));
     for (int l = 0; l < nh; ++l) {
         // B.T0 holds delta_bar_l [R, dout[l]]
         const int out = F->dout[l];
@@ -501,18 +535,18 @@ static int network_backward(tsdfs_field *F, const float *o, const float *v, cons
                 int j = (int)(i - r * inn);
                 Ep[r * W + j] = rs2 * (j < out ? Eb[r * W + j] : gbg[r * dg + (j - out)]);
             });
-            BLAS(gemm_rm(h, false, true, R, outn, inn, 1.0f, B.T2, W, Wl(ln), inn, 0.0f, B.T0, W));
-            BLAS(gemm_rm(h, true, false, outn, inn, R, 1.0f, B.D[ln], W, B.T2, W, 1.0f, gW(ln), inn));
+            BLAS(gemm_rm(G, false, true, R, outn, inn, 1.0f, B.T2, W, Wl(ln), inn, 0.0f, B.T0, W));
+            BLAS(gemm_rm(G, true, false, outn, inn, R, 1.0f, B.D[ln], W, B.T2, W, 1.0f, gW(ln), inn));
         } else {
-            BLAS(gemm_rm(h, false, true, R, outn, inn, 1.0f, B.T1, W, Wl(ln), inn, 0.0f, B.T0, W));
-            BLAS(gemm_rm(h, true, false, outn, inn, R, 1.0f, B.D[ln], W, B.T1, W, 1.0f, gW(ln), inn));
+            BLAS(gemm_rm(G, false, true, R, outn, inn, 1.0f, B.T1, W, Wl(ln), inn, 0.0f, B.T0, W));
+            BLAS(gemm_rm(G, true, false, outn, inn, R, 1.0f, B.D[ln], W, B.T1, W, 1.0f, gW(ln), inn));
         }
     }
     // ---- first-order pass (ordinary backprop of the forward, with the
     // second-order contributions Z2 injected at every hidden layer)
-    BLAS(gemm_rm(h, true, false, ny, W, R, 1.0f, B.Ybar, ny, B.X[nh], W, 1.0f, gW(nh), W));
+    BLAS(gemm_rm(G, true, false, ny, W, R, 1.0f, B.Ybar, ny, B.X[nh], W, 1.0f, gW(nh), W));
     BLAS(colsum(h, R, ny, B.Ybar, ny, B.ones, gb(nh)));
-    BLAS(gemm_rm(h, false, false, R, W, ny, 1.0f, B.Ybar, ny, Wl(nh), W, 0.0f, B.T0, W));
+    BLAS(gemm_rm(G, false, false, R, W, ny, 1.0f, B.Ybar, ny, Wl(nh), W, 0.0f, B.T0, W));
     float hbar_scale = 1.0f;   // 1/sqrt2 when T0 came through the skip input
     for (int l = nh - 1; l >= 0; --l) {
         const int in = F->din[l], out = F->dout[l];
@@ -524,10 +558,10 @@ static int network_backward(tsdfs_field *F, const float *o, const float *v, cons
             int j = (int)(i - r * out);
             Zb[r * W + j] = hsc * Hb[r * W + j] * sig(beta * Z[r * W + j]) + Z2[r * W + j];
         });
-        BLAS(gemm_rm(h, true, false, out, in, R, 1.0f, B.T1, W, B.X[l], in, 1.0f, gW(l), in));
+        BLAS(gemm_rm(G, true, false, out, in, R, 1.0f, B.T1, W, B.X[l], in, 1.0f, gW(l), in));
         BLAS(colsum(h, R, out, B.T1, W, B.ones, gb(l)));
         if (l > 0) {
-            BLAS(gemm_rm(h, false, false, R, in, out, 1.0f, B.T1, W, Wl(l), in, 0.0f, B.T0, W));
+            BLAS(gemm_rm(G, false, false, R, in, out, 1.0f, B.T1, W, Wl(l), in, 0.0f, B.T0, W));
             hbar_scale = (l == skip) ? rs2 : 1.0f;
         }
     }
@@ -559,8 +593,8 @@ int sdf_mlp_bwd(tsdfs_field *F, const float *o, const float *v, const float *t,
     TSDFS_CHECK_ARG(F != nullptr, "field is NULL");
     TSDFS_CHECK_ARG(n_samples >= 0 && n_eik >= 0, "negative sizes");
     TSDFS_CHECK_ARG(n_samples + n_eik < ((int64_t)1 << 31) / 512, "too many rows");
-    if (precision != TSDFS_FP32) {
-        set_error("sdf_mlp_bwd: only FP32 is supported");
+    if (precision != TSDFS_FP32 && precision != TSDFS_BF16) {
+        set_error("sdf_mlp_bwd: precision %d not supported", precision);
         return TSDFS_EUNSUPPORTED;
     }
     TSDFS_CHECK_ARG(d_params_sdf && d_params_color, "NULL gradient output");
@@ -572,7 +606,7 @@ int sdf_mlp_bwd(tsdfs_field *F, const float *o, const float *v, const float *t,
     TSDFS_CHECK_ARG(ws && ws_bytes >= need, "workspace too small (%zu < %zu)", ws_bytes, need);
     int rc = network_backward(F, o, v, t, ray_id, n_samples, eik_x, n_eik, eik_lambda, d_f,
                               d_grad_f, d_rgb, d_params_sdf, d_params_color, (char *)ws,
-                              as_stream(stream), eik_loss);
+                              as_stream(stream), eik_loss, precision == TSDFS_BF16);
     if (rc) return rc;
     TSDFS_LAUNCH_CHECK();
     return TSDFS_OK;

@@ -196,9 +196,10 @@ class Field:
         return f[:S], (g[:S] if full else None), (rgb[:S] if full else None)
 
     def backward(self, o, v, t, ray_id, d_f, d_grad, d_rgb, eik_x=None, eik_lambda=0.0,
-                 d_sdf=None, d_col=None):
-        """Accumulate weight gradients (FP32) into d_sdf / d_col (allocated
-        zeroed when None); returns (d_sdf, d_col, eikonal loss tensor)."""
+                 d_sdf=None, d_col=None, precision=L.FP32):
+        """Accumulate weight gradients (FP32 outputs; products in FP32 or with
+        BF16 inputs) into d_sdf / d_col (allocated zeroed when None); returns
+        (d_sdf, d_col, eikonal loss tensor)."""
         d = _dev()
         S = t.shape[0] if t is not None else 0
         P = eik_x.shape[0] if eik_x is not None else 0
@@ -211,7 +212,7 @@ class Field:
         ws = torch.empty(max(b.value, 256), dtype=torch.uint8, device=d)
         eik = torch.zeros(1, dtype=torch.float32, device=d)
         L.check(L.load().sdf_mlp_bwd(self.handle, _p(o), _p(v), _p(t), _p(ray_id), S, _p(eik_x), P,
-                                     float(eik_lambda), _p(d_f), _p(d_grad), _p(d_rgb), L.FP32,
+                                     float(eik_lambda), _p(d_f), _p(d_grad), _p(d_rgb), precision,
                                      _p(d_sdf), _p(d_col), _p(eik), _p(ws), ws.numel(), _stream()))
         return d_sdf, d_col, eik
 
