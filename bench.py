@@ -28,6 +28,33 @@ sys.path.insert(0, ROOT)
 PEAK_TFLOPS = {"f32": 157.3, "bf16": 2500.0}
 HBM_PEAK_GBS = 8000.0
 
+# HBM traffic of one 6.02 M-sample field launch on the c2 view, from the
+# FETCH_SIZE / WRITE_SIZE counters (KiB per dispatch) of the kernel built from
+# the sources whose digest is given; scaled by a plain copy's counters
+# (fetch x 2, write x 1).  Reported only while the sources still match.
+FIELD_SOURCES = {"k_field_fp32": ["field_fp32.hip", "field_common.hpp", "common.hpp", "field.hip"],
+                 "k_field_bf16": ["field_bf16.hip", "field_common.hpp", "common.hpp", "field.hip"]}
+TRAFFIC = {
+    "k_field_fp32": {"sha256_16": "580c3d1a41255800", "fetch_kib": 3.383e7, "write_kib": 5.786e7},
+    "k_field_bf16": {"sha256_16": "08274f2344e4a306", "fetch_kib": 2.018e7, "write_kib": 2.088e7},
+}
+COPY_SCALE = {"fetch": 2.0, "write": 1.0}
+
+
+def field_traffic_bytes(kernel, workload):
+    """Measured HBM bytes per launch, or None when the kernel changed since."""
+    import hashlib
+    t = TRAFFIC.get(kernel)
+    if t is None or workload != "c2":
+        return None
+    m = hashlib.sha256()
+    for f in FIELD_SOURCES[kernel]:
+        with open(os.path.join(ROOT, "paper_2311_17878_amd", "csrc", f), "rb") as fh:
+            m.update(fh.read())
+    if m.hexdigest()[:16] != t["sha256_16"]:
+        return None
+    return 1024.0 * (t["fetch_kib"] * COPY_SCALE["fetch"] + t["write_kib"] * COPY_SCALE["write"])
+
 
 def field_flops_per_sample(sdf, col):
     """Algorithmic FLOP of one full field evaluation: SDF forward, reverse
@@ -67,6 +94,21 @@ def cpu_baseline(cfg, ro, rv, n_rays, seed=0):
                 sample=f"{n_rays} seeded rays of the view through the FP64 oracle render path "
                        f"(bounds, placement, field, compositing) with the oracle's stored flags; "
                        f"{int(p['offsets'][-1])} samples; {dt:.1f} s")
+
+
+def stage_hbm(stage_ms, n_rays, S, total_steps):
+    work = {
+        "bounds": 24 * n_rays + 17 * n_rays + total_steps,       # o, v in; t_n, t_f, ids out; 1 B/step
+        "place": 13 * n_rays + 8 * n_rays + 12 * S,              # bounds in; count, offset; t, dt, ray_id
+        "composite": 36 * S + 32 * n_rays,                       # t, dt, f, grad f, rgb; ray outputs
+    }
+    out = {}
+    for k, b in work.items():
+        if k in stage_ms and stage_ms[k] > 0:
+            gbs = b / (stage_ms[k] * 1e-3) / 1e9
+            out[k] = {"bytes": b, "GB_per_s": gbs, "frac": gbs / HBM_PEAK_GBS}
+    out["dda_steps"] = total_steps
+    return out
 
 
 def main():
@@ -161,6 +203,8 @@ def main():
     counts = chk["place"]["counts"].cpu().numpy()
     status = chk["bounds"]["status"].cpu().numpy()
     nz = counts[counts > 0]
+    nsteps = ops.ray_bounds(R.grid, R.flags, ro_d, rv_d, R.t_far, steps=True)["n_steps"]
+    total_steps = int(nsteps.sum().item())
     fl_sample, fl_sdf_only = field_flops_per_sample(cfg.sdf, cfg.color)
     field_ms = stage_ms["field"]
     achieved = S * fl_sample / (field_ms * 1e-3) / 1e12
@@ -200,6 +244,9 @@ def main():
             "samples": S,
         },
         "stage_ms": stage_ms,
+        # algorithmic bytes of the HBM-bound stages (per ray / sample / DDA step), their GB/s
+        # over the stage's event time, and the fraction of the 8 TB/s HBM peak
+        "stage_hbm": stage_hbm(stage_ms, n_rays, S, total_steps),
         "roofline": {
             "kernel": "k_field_fp32" if prec == _lib.FP32 else "k_field_bf16",
             "bound": "mfma",
@@ -207,12 +254,17 @@ def main():
             "peak": PEAK_TFLOPS[dtype],
             "unit": "TFLOP/s",
             "frac": achieved / PEAK_TFLOPS[dtype],
-            "traffic": None,
+            "traffic": field_traffic_bytes("k_field_fp32" if prec == _lib.FP32 else "k_field_bf16",
+                                           cfg.name),
+            "traffic_unit": "bytes per launch (HBM, counters)",
             "flop_per_sample": fl_sample,
         },
         "integrate": {
             "rays": int(o.shape[0]), "ms": integ_ms, "rays_per_s": o.shape[0] / (integ_ms * 1e-3),
             "voxel_updates": updates, "updates_per_s": updates / (integ_ms * 1e-3),
+            # 28 B per ray + a 12 B read-modify-write (int64 sum, uint32 count) per update
+            "hbm_GB_per_s": (28 * o.shape[0] + 24 * updates) / (integ_ms * 1e-3) / 1e9,
+            "hbm_frac": (28 * o.shape[0] + 24 * updates) / (integ_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
             "finalize_ms": fin_ms,
             "paper_context": "1.445e6 rays/s (0.692 us/ray, 39.0 M rays in 27.02 s, GPU unnamed)",
         },
@@ -242,7 +294,9 @@ def main():
             "ms_per_step": ms_o, "rays_per_s": n_rays / (ms_o * 1e-3), "field_ms": field_o,
             "roofline": {"kernel": "k_field_bf16" if other == _lib.BF16 else "k_field_fp32",
                          "bound": "mfma", "achieved": ach_o, "peak": PEAK_TFLOPS[oname],
-                         "unit": "TFLOP/s", "frac": ach_o / PEAK_TFLOPS[oname]},
+                         "unit": "TFLOP/s", "frac": ach_o / PEAK_TFLOPS[oname],
+                         "traffic": field_traffic_bytes(
+                             "k_field_bf16" if other == _lib.BF16 else "k_field_fp32", cfg.name)},
         }
         log(f"{oname}: {ms_o:.3f} ms/step")
 
