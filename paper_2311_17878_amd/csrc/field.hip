@@ -280,8 +280,10 @@ int tsdfs_field_destroy(tsdfs_field *F) {
 
 int sdf_mlp_fwd_ws_bytes(const tsdfs_field *F, size_t *bytes) {
     TSDFS_CHECK_ARG(F && bytes, "NULL argument");
-    // one slot per resident workgroup (up to two per compute unit)
-    *bytes = (size_t)2 * F->n_wg * slot_floats(F->plan.n_hidden) * sizeof(float);
+    // one slot per resident workgroup, for either kernel
+    const size_t a = slot_floats(F->plan.n_hidden);
+    const size_t b = (size_t)kBWGPerCU * bf16_slot_floats(F->plan.n_hidden);
+    *bytes = (size_t)F->n_wg * (a > b ? a : b) * sizeof(float);
     return TSDFS_OK;
 }
 
@@ -301,9 +303,10 @@ int sdf_mlp_fwd(const tsdfs_field *F, const float *o, const float *v, const floa
     size_t need;
     sdf_mlp_fwd_ws_bytes(F, &need);
     TSDFS_CHECK_ARG(ws && ws_bytes >= need, "workspace too small (%zu < %zu)", ws_bytes, need);
-    const int64_t tiles = (s_cap + kTile - 1) / kTile;
-    // persistent grids: two BF16 workgroups fit a compute unit, one FP32
-    const int64_t max_grid = precision == TSDFS_BF16 ? 2 * (int64_t)F->n_wg : F->n_wg;
+    // persistent grids: as many workgroups as fit the compute units
+    const int tile = precision == TSDFS_BF16 ? kBTile : kTile;
+    const int64_t tiles = (s_cap + tile - 1) / tile;
+    const int64_t max_grid = (precision == TSDFS_BF16 ? kBWGPerCU : 1) * (int64_t)F->n_wg;
     const int grid = (int)(tiles < max_grid ? tiles : max_grid);
     if (precision == TSDFS_BF16)
         launch_field_bf16(F->bplan, grid, o, v, t, ray_id, s_cap, s_count_dev, f, grad_f, rgb,

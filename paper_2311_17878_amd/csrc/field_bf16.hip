@@ -23,8 +23,11 @@
 
 namespace tsdfs {
 
+constexpr int kBT = kBTile;                   // samples per tile
+constexpr int kCB = kBT / 32;                 // 32-sample column blocks per tile
 constexpr int kBWaves = 4;
 constexpr int kBThreads = kBWaves * 64;
+constexpr int kColGroups = kBWaves / 4;       // waves sharing a row pair
 constexpr int kStride = 280;                  // bf16 elements per sample row in LDS
 
 typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
@@ -35,8 +38,11 @@ __device__ __forceinline__ uint32_t pk(float a, float b) {
     return __builtin_bit_cast(uint32_t, __builtin_convertvector(f, bf16x2));  // RNE
 }
 
-// Share of one layer's output for one wave: row tiles t0 (and t1 >= 0),
-// column blocks c0 .. c0 + nc - 1.  t0 < 0: no share.
+// Share of one layer for one wave: row tiles t0 (and t1 >= 0), column
+// blocks c0 .. c0 + nc - 1 of the tile's kCB.  t0 < 0: no share.  Layers of
+// more than four row tiles: row pair (wave % 4, + 4) x the column blocks of
+// group wave / 4; smaller ones: blocks b = wave and wave + kBWaves
+// (b = kCB t + c).
 struct Split {
     int t0, t1, c0, nc;
 };
@@ -44,25 +50,22 @@ struct Split {
 __device__ __forceinline__ Split split_of(int n_t, int wave) {
     Split s;
     if (n_t > 4) {
-        s.t0 = wave;
-        s.t1 = wave + 4 < n_t ? wave + 4 : -1;
-        s.c0 = 0;
-        s.nc = 4;
-    } else if (n_t >= 3) {
+        const int rp = wave & 3;
+        s.t0 = rp;
+        s.t1 = rp + 4 < n_t ? rp + 4 : -1;
+        s.nc = kCB / kColGroups;
+        s.c0 = (wave >> 2) * s.nc;
+    } else if (n_t * kCB <= 2 * kBWaves) {
+        const int nb = n_t * kCB;
+        s.t0 = wave < nb ? wave / kCB : -1;
+        s.t1 = wave + kBWaves < nb ? (wave + kBWaves) / kCB : -1;
+        s.c0 = wave % kCB;
+        s.nc = 1;
+    } else {                       // one row tile per wave, every column block
         s.t0 = wave < n_t ? wave : -1;
         s.t1 = -1;
         s.c0 = 0;
-        s.nc = 4;
-    } else if (n_t == 2) {
-        s.t0 = wave & 1;
-        s.t1 = -1;
-        s.c0 = (wave >> 1) * 2;
-        s.nc = 2;
-    } else {
-        s.t0 = 0;
-        s.t1 = -1;
-        s.c0 = wave;
-        s.nc = 1;
+        s.nc = kCB;
     }
     return s;
 }
@@ -100,11 +103,17 @@ __device__ __forceinline__ void gemm_t(const BLayer &L, const __bf16 *act,
     if (NT == 2) ao[NT - 1] = (unsigned)opq(s.t1 * K16 * 64 + lane);
     const __bf16 *bp = act + (s.c0 * 32 + col) * kStride + khalf * 8;
     bf16x8 a0[NT], a1[NT], a2[NT], b0[NC], b1[NC], b2[NC];
-    auto load = [&](bf16x8 (&a)[NT], bf16x8 (&b)[NC], int k) __attribute__((always_inline)) {
+    auto loadA = [&](bf16x8 (&a)[NT], int k) __attribute__((always_inline)) {
 #pragma unroll
         for (int tt = 0; tt < NT; ++tt) a[tt] = W[ao[tt] + (unsigned)k * 64u];
+    };
+    auto loadB = [&](bf16x8 (&b)[NC], int k) __attribute__((always_inline)) {
 #pragma unroll
         for (int j = 0; j < NC; ++j) b[j] = *(const bf16x8 *)(bp + j * 32 * kStride + k * 16);
+    };
+    auto load = [&](bf16x8 (&a)[NT], bf16x8 (&b)[NC], int k) __attribute__((always_inline)) {
+        loadA(a, k);
+        loadB(b, k);
     };
     auto mma = [&](const bf16x8 (&a)[NT], const bf16x8 (&b)[NC]) __attribute__((always_inline)) {
 #pragma unroll
@@ -174,16 +183,21 @@ template <class Pre, class Epi>
 __device__ __forceinline__ void run_layer(const BLayer &L, const __bf16 *act, int wave, int lane,
                                           bool sync, Pre pre, Epi epi) {
     const Split s = split_of(L.n_tiles, wave);
+    constexpr int NP = kCB / kColGroups;   // column blocks of a row-pair share
     if (s.t0 < 0) {
         if (sync) __syncthreads();
-    } else if (s.nc == 4 && s.t1 >= 0) {
-        layer_t<2, 4>(L, act, s, lane, sync, pre, epi);
-    } else if (s.nc == 4) {
-        layer_t<1, 4>(L, act, s, lane, sync, pre, epi);
-    } else if (s.nc == 2) {
-        layer_t<1, 2>(L, act, s, lane, sync, pre, epi);
+    } else if (s.nc == NP) {
+        if (s.t1 >= 0)
+            layer_t<2, NP>(L, act, s, lane, sync, pre, epi);
+        else
+            layer_t<1, NP>(L, act, s, lane, sync, pre, epi);
+    } else if (s.nc == 1) {
+        if (s.t1 >= 0)
+            layer_t<2, 1>(L, act, s, lane, sync, pre, epi);
+        else
+            layer_t<1, 1>(L, act, s, lane, sync, pre, epi);
     } else {
-        layer_t<1, 1>(L, act, s, lane, sync, pre, epi);
+        layer_t<1, kCB>(L, act, s, lane, sync, pre, epi);
     }
 }
 
@@ -204,24 +218,27 @@ __device__ __forceinline__ void blocks_t(const Split &s, Ld &ld, Use &use) {
 
 template <class Ld, class Use>
 __device__ __forceinline__ void blocks(const Split &s, Ld ld, Use use) {
+    constexpr int NP = kCB / kColGroups;
     if (s.t0 < 0) return;
-    if (s.nc == 4 && s.t1 >= 0)
-        blocks_t<2, 4>(s, ld, use);
-    else if (s.nc == 4)
-        blocks_t<1, 4>(s, ld, use);
-    else if (s.nc == 2)
-        blocks_t<1, 2>(s, ld, use);
-    else
+    if (s.nc == NP && s.t1 >= 0)
+        blocks_t<2, NP>(s, ld, use);
+    else if (s.nc == NP)
+        blocks_t<1, NP>(s, ld, use);
+    else if (s.nc == 1 && s.t1 >= 0)
+        blocks_t<2, 1>(s, ld, use);
+    else if (s.nc == 1)
         blocks_t<1, 1>(s, ld, use);
+    else
+        blocks_t<1, kCB>(s, ld, use);
 }
 
 // Scratch offsets in uint4: softplus' codes [layer][tile][c][lane] (16
 // bytes), then the features [tile][c][lane] (16 bf16, two uint4).
 __device__ __forceinline__ int ssp(int l, int t, int c, int lane) {
-    return ((l * 8 + t) * 4 + c) * 64 + lane;
+    return ((l * 8 + t) * kCB + c) * 64 + lane;
 }
 __device__ __forceinline__ int sft(int n_hidden, int t, int c, int lane) {
-    return n_hidden * 2048 + ((t * 4 + c) * 64 + lane) * 2;
+    return n_hidden * 8 * kCB * 64 + ((t * kCB + c) * 64 + lane) * 2;
 }
 
 // 8-bit code of softplus' (in [0, 1]): round(255 sigma), from 255 sigma.
@@ -261,12 +278,12 @@ __device__ __forceinline__ void softplus2(float z, float kb, float c1, float &h,
 // (frequency, axis, sample).
 __device__ __forceinline__ void encode_tile(int tid, const float *s_xh, int pe, float *gam,
                                             float *jac, __bf16 *act, int k_pad) {
-    for (int idx = tid; idx < 3 * (pe + 1) * kTile; idx += kBThreads) {
-        const int c = idx % kTile, ka = idx / kTile, a = ka % 3, k = ka / 3 - 1;
-        const float x = s_xh[a * kTile + c];
+    for (int idx = tid; idx < 3 * (pe + 1) * kBT; idx += kBThreads) {
+        const int c = idx % kBT, ka = idx / kBT, a = ka % 3, k = ka / 3 - 1;
+        const float x = s_xh[a * kBT + c];
         if (k < 0) {
-            gam[a * kTile + c] = x;
-            jac[a * kTile + c] = 1.0f;
+            gam[a * kBT + c] = x;
+            jac[a * kBT + c] = 1.0f;
             act[c * kStride + a] = (__bf16)x;
             continue;
         }
@@ -274,15 +291,15 @@ __device__ __forceinline__ void encode_tile(int tid, const float *s_xh, int pe, 
         float sn, cs;
         sincosf(sc * x, &sn, &cs);
         const int js = 3 + 6 * k + a, jc = js + 3;
-        gam[js * kTile + c] = sn;
-        jac[js * kTile + c] = sc * cs;
-        gam[jc * kTile + c] = cs;
-        jac[jc * kTile + c] = -sc * sn;
+        gam[js * kBT + c] = sn;
+        jac[js * kBT + c] = sc * cs;
+        gam[jc * kBT + c] = cs;
+        jac[jc * kBT + c] = -sc * sn;
         act[c * kStride + js] = (__bf16)sn;
         act[c * kStride + jc] = (__bf16)cs;
     }
     const int d_gamma = 3 + 6 * pe, n = k_pad - d_gamma;
-    for (int idx = tid; idx < n * kTile; idx += kBThreads)
+    for (int idx = tid; idx < n * kBT; idx += kBThreads)
         act[(idx / n) * kStride + d_gamma + idx % n] = (__bf16)0.0f;
 }
 
@@ -291,13 +308,13 @@ __device__ __forceinline__ void encode_tile(int tid, const float *s_xh, int pe, 
 // its stores.
 __device__ __forceinline__ void inject_gamma(int tid, __bf16 *act, int r0, int d_gamma,
                                              const float *gam) {
-    constexpr int kRowsPerPass = kBThreads / kTile;   // 2
-    const int c = tid % kTile, j0 = tid / kTile;
+    constexpr int kRowsPerPass = kBThreads / kBT;   // 2
+    const int c = tid % kBT, j0 = tid / kBT;
     const float *g = gam + c;
     float x[kGammaRows / kRowsPerPass];
 #pragma unroll
     for (int i = 0; i < kGammaRows / kRowsPerPass; ++i)
-        x[i] = g[min(j0 + kRowsPerPass * i, d_gamma - 1) * kTile];
+        x[i] = g[min(j0 + kRowsPerPass * i, d_gamma - 1) * kBT];
 #pragma unroll
     for (int i = 0; i < kGammaRows / kRowsPerPass; ++i) {
         const int j = j0 + kRowsPerPass * i;
@@ -309,9 +326,9 @@ __device__ __forceinline__ void inject_gamma(int tid, __bf16 *act, int r0, int d
 __device__ __forceinline__ void gamma_grad_reduce(int tid, const float *eg, const float *jac,
                                                   int pe, float *s_g) {
     constexpr int kMaxPe = (kGammaRows - 3) / 6;   // 10
-    for (int idx = tid; idx < 3 * kTile; idx += kBThreads) {
-        const int a = idx / kTile, c = idx % kTile;
-        const int base = a * kTile + c;
+    for (int idx = tid; idx < 3 * kBT; idx += kBThreads) {
+        const int a = idx / kBT, c = idx % kBT;
+        const int base = a * kBT + c;
         float e[1 + 2 * kMaxPe], d[1 + 2 * kMaxPe];
 #pragma unroll
         for (int i = 0; i < 1 + 2 * kMaxPe; ++i) {
@@ -319,33 +336,33 @@ __device__ __forceinline__ void gamma_grad_reduce(int tid, const float *eg, cons
             // the encoding read row a again and are dropped
             const bool live = i < 1 + 2 * pe;
             const int j = (i == 0 || !live) ? 0 : 3 + 6 * ((i - 1) >> 1) + 3 * ((i - 1) & 1);
-            e[i] = eg[base + j * kTile];
-            d[i] = live ? jac[base + j * kTile] : 0.0f;
+            e[i] = eg[base + j * kBT];
+            d[i] = live ? jac[base + j * kBT] : 0.0f;
         }
         float sum = 0.0f;
 #pragma unroll
         for (int i = 0; i < 1 + 2 * kMaxPe; ++i) sum = fmaf(e[i], d[i], sum);
-        s_g[a * kTile + c] += sum;
+        s_g[a * kBT + c] += sum;
     }
 }
 
 // act rows [r0, r1) <- 0
 __device__ __forceinline__ void zero_rows(int tid, __bf16 *act, int r0, int r1) {
     const int n = r1 - r0;
-    for (int idx = tid; idx < n * kTile; idx += kBThreads)
+    for (int idx = tid; idx < n * kBT; idx += kBThreads)
         act[(idx / n) * kStride + r0 + idx % n] = (__bf16)0.0f;
 }
 
 template <bool FULL>
-__global__ void __launch_bounds__(kBThreads, 2)
+__global__ void __launch_bounds__(kBThreads, kBWGPerCU * kBWaves / 4)
 k_field_bf16(const BPlan P, const float *__restrict__ o, const float *__restrict__ v,
              const float *__restrict__ tval, const int32_t *__restrict__ ray_id, int64_t s_cap,
              const int64_t *__restrict__ s_count, float *__restrict__ f_out,
              float *__restrict__ g_out, float *__restrict__ rgb_out, float *__restrict__ ws) {
-    __shared__ __attribute__((aligned(16))) __bf16 act[kTile * kStride];
-    __shared__ float s_xh[3 * kTile];
-    __shared__ float s_v[3 * kTile];
-    __shared__ float s_g[3 * kTile];
+    __shared__ __attribute__((aligned(16))) __bf16 act[kBT * kStride];
+    __shared__ float s_xh[3 * kBT];
+    __shared__ float s_v[3 * kBT];
+    __shared__ float s_g[3 * kBT];
 
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     int64_t S = s_cap;
@@ -353,14 +370,14 @@ k_field_bf16(const BPlan P, const float *__restrict__ o, const float *__restrict
         int64_t c = *s_count;
         S = c < s_cap ? c : s_cap;
     }
-    const int64_t n_tiles = (S + kTile - 1) / kTile;
-    // slot: softplus' codes [n_hidden][8][4][64][16 B], features
-    // [8][4][64][32 B], then (at (n_hidden + 1) x 64 KiB) FP32 eg, gam, jac [64][128]
-    float *slot = ws + (size_t)blockIdx.x * slot_floats(P.n_hidden);
+    const int64_t n_tiles = (S + kBT - 1) / kBT;
+    // slot: softplus' codes [n_hidden][8][kCB][64][16 B], features
+    // [8][kCB][64][32 B], then FP32 eg, gam, jac [64][kBT]
+    float *slot = ws + (size_t)blockIdx.x * bf16_slot_floats(P.n_hidden);
     uint4 *scr = (uint4 *)slot;
-    float *eg = slot + (size_t)(P.n_hidden + 1) * (kScratchLayer / 2);
-    float *gam = eg + kGammaRows * kTile;
-    float *jac = gam + kGammaRows * kTile;
+    float *eg = slot + (size_t)(P.n_hidden * 8 * kCB * 64 + 8 * kCB * 128) * 4;
+    float *gam = eg + kGammaRows * kBT;
+    float *jac = gam + kGammaRows * kBT;
     const float kb = P.kb, c1 = P.c1;
     const int pe = (P.d_gamma - 3) / 6;
 
@@ -370,8 +387,8 @@ k_field_bf16(const BPlan P, const float *__restrict__ o, const float *__restrict
         // the tile loop
         const int tid = opq((int)threadIdx.x);
         const int lane = tid & 63, col = lane & 31, khalf = lane >> 5;
-        const int64_t s0 = tile * kTile;
-        if (tid < kTile) {
+        const int64_t s0 = tile * kBT;
+        if (tid < kBT) {
             int64_t s = s0 + tid;
             float xh[3] = {0.f, 0.f, 0.f}, vv[3] = {0.f, 0.f, 0.f};
             if (s < S) {
@@ -386,9 +403,9 @@ k_field_bf16(const BPlan P, const float *__restrict__ o, const float *__restrict
             }
 #pragma unroll
             for (int a = 0; a < 3; ++a) {
-                s_xh[a * kTile + tid] = xh[a];
-                s_v[a * kTile + tid] = vv[a];
-                s_g[a * kTile + tid] = 0.0f;
+                s_xh[a * kBT + tid] = xh[a];
+                s_v[a * kBT + tid] = vv[a];
+                s_g[a * kBT + tid] = 0.0f;
             }
         }
         __syncthreads();
@@ -498,7 +515,7 @@ k_field_bf16(const BPlan P, const float *__restrict__ o, const float *__restrict
 #pragma unroll
                         for (int u = 0; u < 4; ++u) {
                             if (r0 + u >= n_prev) {
-                                eg[(r0 + u - n_prev) * kTile + cc] = a[4 * q + u];
+                                eg[(r0 + u - n_prev) * kBT + cc] = a[4 * q + u];
                                 e[u] = 0.0f;
                             }
                         }
@@ -513,11 +530,11 @@ k_field_bf16(const BPlan P, const float *__restrict__ o, const float *__restrict
             }
         }
         // ---- grad f out; colour input [feat, x_hat, v, grad f]
-        if (tid < kTile) {
+        if (tid < kBT) {
             int64_t s = s0 + tid;
             if (s < S) {
 #pragma unroll
-                for (int a = 0; a < 3; ++a) g_out[3 * s + a] = s_g[a * kTile + tid];
+                for (int a = 0; a < 3; ++a) g_out[3 * s + a] = s_g[a * kBT + tid];
             }
         }
         blocks(split_of(P.feat.n_tiles, wave),
@@ -529,10 +546,10 @@ k_field_bf16(const BPlan P, const float *__restrict__ o, const float *__restrict
                [&](int t, int c, uint4 (&b)[2]) __attribute__((always_inline)) {
                    st_rows(t, c, b[0].x, b[0].y, b[0].z, b[0].w, b[1].x, b[1].y, b[1].z, b[1].w);
                });
-        for (int idx = tid; idx < 9 * kTile; idx += kBThreads) {
+        for (int idx = tid; idx < 9 * kBT; idx += kBThreads) {
             int c = idx / 9, j = idx % 9;
-            float x = j < 3 ? s_xh[j * kTile + c]
-                            : (j < 6 ? s_v[(j - 3) * kTile + c] : s_g[(j - 6) * kTile + c]);
+            float x = j < 3 ? s_xh[j * kBT + c]
+                            : (j < 6 ? s_v[(j - 3) * kBT + c] : s_g[(j - 6) * kBT + c]);
             act[c * kStride + P.n_feat + j] = (__bf16)x;
         }
         if (P.n_feat + 9 < P.col[0].K16 * 16) zero_rows(tid, act, P.n_feat + 9, P.col[0].K16 * 16);

@@ -20,6 +20,15 @@ constexpr int kScratchLayer = 8 * 4 * 16 * 64;
 __host__ __device__ constexpr size_t slot_floats(int n_hidden) {
     return (size_t)(n_hidden + 1) * kScratchLayer + 3 * kGammaRows * kTile;
 }
+// BF16 kernel: kBWGPerCU workgroups per compute unit, tiles of kBTile
+// samples; slot = softplus' codes (kBTile x 256 bytes per hidden layer),
+// BF16 features (kBTile x 512 bytes), encoding / Jacobian / d f / d gamma
+// (3 x 64 x kBTile floats)
+constexpr int kBTile = 128;
+constexpr int kBWGPerCU = 2;
+__host__ __device__ constexpr size_t bf16_slot_floats(int n_hidden) {
+    return (size_t)n_hidden * kBTile * 64 + kBTile * 128 + 3 * kGammaRows * kBTile;
+}
 
 // FP32 A operand of v_mfma_f32_32x32x2_f32, packed [n_tiles][K8/8][64 lanes][4]
 // (lane l, element j of group g: row l%32, column 2 (4g + j) + l/32).
