@@ -8,6 +8,14 @@ T_i = prod_{j<i} (1 - alpha_j); depth (Eq. 2): D = sum w_i t_i / sum w_i with
 w_i = T_i alpha_i; normal (supplementary, "Normal Estimation"):
 N = sum w_i n_i / sum w_i, n = grad f / |grad f|.
 
+Coarse + fine sampling inside the TSDF bound (the "Ours (full)" rows of the
+experiment tables; the supplementary ray-distribution analysis): the
+adaptive samples of a ray are its coarse set, fine points are drawn from the
+coarse weight distribution by inverse transform sampling (the hierarchical
+sampling paragraph: normalised coarse weights), and the merged points are
+rendered.  full_upsample applies the baseline's hs_upsample / hs_sections to
+each ray's own coarse set.
+
 Opacity from the SDF ("density transformed from SDF", below Eq. 1): the NeuS
 discrete opacity of a section [t - dt/2, t + dt/2],
 alpha = max((Phi(f_prev) - Phi(f_next)) / Phi(f_prev), 0),  Phi(x) = sigmoid(s x),
@@ -135,3 +143,40 @@ def hs_sections(z_coarse, z_fine, t_out):
     y = np.sort(np.concatenate([z_coarse, z_fine], axis=1), axis=1)
     ends = np.concatenate([y[:, 1:], np.asarray(t_out, np.float64)[:, None]], axis=1)
     return 0.5 * (y + ends), ends - y
+
+
+def full_upsample(offsets, t_c, dt_c, f_c, t_f, s, n_fine):
+    """Fine samples inside the TSDF bound for ragged coarse sets.
+
+    Ray r owns coarse samples offsets[r] .. offsets[r+1]-1 (positions t_c
+    ascending, lengths dt_c, SDF f_c).  A ray with n >= 2 coarse points gets
+    n_fine fine points (hs_upsample of its n points), and its samples become
+    the sections of the merged points (hs_sections, the last ending at
+    t_f[r]); a ray with n < 2 keeps its coarse samples.  Returns counts,
+    offsets [R+1], t, dt, ray_id (ray order).
+    """
+    offsets = np.asarray(offsets, np.int64)
+    t_c = np.asarray(t_c, np.float64)
+    dt_c = np.asarray(dt_c, np.float64)
+    f_c = np.asarray(f_c, np.float64)
+    t_f = np.asarray(t_f, np.float64)
+    R = offsets.shape[0] - 1
+    counts = np.zeros(R, np.int64)
+    ts, dts, rids = [], [], []
+    for r in range(R):
+        a, b = offsets[r], offsets[r + 1]
+        n = b - a
+        if n < 2:
+            t_r, dt_r = t_c[a:b], dt_c[a:b]
+        else:
+            z = t_c[a:b][None]
+            fine = hs_upsample(z, f_c[a:b][None], s, n_fine)
+            t_r, dt_r = hs_sections(z, fine, t_f[r:r + 1])
+            t_r, dt_r = t_r[0], dt_r[0]
+        counts[r] = t_r.shape[0]
+        ts.append(t_r)
+        dts.append(dt_r)
+        rids.append(np.full(t_r.shape[0], r, np.int64))
+    off = np.concatenate([[0], np.cumsum(counts)])
+    cat = lambda x: np.concatenate(x) if x else np.zeros(0)
+    return counts, off, cat(ts), cat(dts), cat(rids).astype(np.int64)

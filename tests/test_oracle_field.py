@@ -161,3 +161,55 @@ def test_hs_upsample_concentrates_at_the_surface():
     assert (np.diff(fine[0]) >= 0).all()
     t, dt = Rn.hs_sections(z, fine, np.array([4.0]))
     assert (dt >= 0).all() and dt.sum() == pytest.approx(4.0, abs=1e-12)
+
+
+def test_full_upsample_ragged_closed_forms():
+    """Coarse + fine inside the bound, ragged coarse sets: with zero opacity
+    the coarse weights are uniform, so the fine points are the stratified
+    quantiles z_0 + u_m (z_{n-1} - z_0) of each ray's own range; rays with
+    fewer than two coarse points keep them; the sections tile [z_0, t_f]."""
+    n_fine = 8
+    ns = [0, 1, 2, 5, 17, 64, 3]
+    lengths = np.array([0.0, 2.0, 3.0, 5.5, 9.0, 4.0, 1.0])
+    t_f = 0.25 * np.arange(len(ns)) + lengths
+    t_c, dt_c, f_c, off = [], [], [], [0]
+    for r, n in enumerate(ns):
+        d = lengths[r] / max(n, 1)
+        z = 0.25 * r + (np.arange(n) + 0.5) * d
+        t_c.append(z)
+        dt_c.append(np.full(n, d))
+        f_c.append(np.full(n, 5.0))                # far outside every surface: alpha = 0
+        off.append(off[-1] + n)
+    t_c, dt_c, f_c = map(np.concatenate, (t_c, dt_c, f_c))
+    counts, o2, t, dt, rid = Rn.full_upsample(np.array(off), t_c, dt_c, f_c, t_f, 64.0, n_fine)
+    u = (np.arange(n_fine) + 0.5) / n_fine
+    for r, n in enumerate(ns):
+        a, b = o2[r], o2[r + 1]
+        assert (rid[a:b] == r).all()
+        zc = t_c[off[r]:off[r + 1]]
+        if n < 2:
+            assert counts[r] == n
+            np.testing.assert_array_equal(t[a:b], zc)
+            np.testing.assert_array_equal(dt[a:b], dt_c[off[r]:off[r + 1]])
+            continue
+        assert counts[r] == n + n_fine
+        fine = zc[0] + u * (zc[-1] - zc[0])
+        y = np.sort(np.concatenate([zc, fine]))
+        e = np.append(y[1:], t_f[r])
+        np.testing.assert_allclose(t[a:b], 0.5 * (y + e), rtol=0, atol=1e-12)
+        np.testing.assert_allclose(dt[a:b], e - y, rtol=0, atol=1e-12)
+        assert dt[a:b].sum() == pytest.approx(t_f[r] - zc[0], abs=1e-12)
+
+
+def test_full_upsample_concentrates_at_the_crossing():
+    """A plane crossing inside a ray's bound: half the fine points fall
+    within one coarse spacing of it."""
+    n, n_fine = 12, 32
+    z = 1.0 + (np.arange(n) + 0.5) * 0.25
+    f = 2.3 - z                                    # crossing at t = 2.3
+    counts, o2, t, dt, rid = Rn.full_upsample(np.array([0, n]), z, np.full(n, 0.25), f,
+                                              np.array([4.0]), 64.0, n_fine)
+    edges = np.append(t - dt / 2, 4.0)
+    fine = np.setdiff1d(np.round(edges[:-1], 12), np.round(z, 12))
+    assert fine.size == n_fine
+    assert np.median(fine) == pytest.approx(2.3, abs=0.25)
