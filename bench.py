@@ -124,6 +124,8 @@ def main():
     ap.add_argument("--no-hs", action="store_true")
     ap.add_argument("--no-other", action="store_true", help="skip the other-precision leg")
     ap.add_argument("--no-train", action="store_true", help="skip the training-step leg")
+    ap.add_argument("--full-fine", type=int, default=8,
+                    help="fine samples per ray of the coarse + fine leg (0: skip the leg)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a device-to-device copy of MIB MiB (to scale HBM counters)")
     args = ap.parse_args()
@@ -300,6 +302,33 @@ def main():
         }
         log(f"{oname}: {ms_o:.3f} ms/step")
 
+    # ---- coarse + fine inside the TSDF bound ("Ours (full)"): the adaptive
+    # samples as coarse sets (SDF only), n_fine fine points per ray, the field
+    # at the merged sections, compositing
+    full_ms = None
+    if args.full_fine > 0:
+        nf = args.full_fine
+        for _ in range(args.warmup):
+            R.render_full(ro_d, rv_d, nf)
+        ev_f = {}
+        torch.cuda.synchronize()
+        start.record()
+        for _ in range(args.steps):
+            out_f = R.render_full(ro_d, rv_d, nf, events=ev_f)
+        end.record()
+        torch.cuda.synchronize()
+        full_ms = start.elapsed_time(end) / args.steps
+        S_f = int(out_f["s_total"].item())
+        result[f"full_{nf}"] = {
+            "ms_per_step": full_ms, "rays_per_s": n_rays / (full_ms * 1e-3), "n_fine": nf,
+            "precision": dtype,
+            "samples_per_ray": {"coarse_sdf_only": S / n_rays, "rendered": S_f / n_rays,
+                                "field_evaluations": (S + S_f) / n_rays},
+            "stage_ms": {k: float(np.mean([a.elapsed_time(b) for a, b in v_]))
+                         for k, v_ in ev_f.items()},
+        }
+        log(f"full (+{nf} fine): {full_ms:.3f} ms/step, {S_f / n_rays:.2f} rendered samples/ray")
+
     # ---- one TSDF-bounded training step (8192 rays + 8192 eikonal points)
     if cfg.name in ("c2", "c3", "c4") and not args.no_train:
         from paper_2311_17878_amd.autograd import train_step
@@ -341,6 +370,7 @@ def main():
             "stage_ms": {k: float(np.mean([a.elapsed_time(b) for a, b in v_]))
                          for k, v_ in ev_hs.items()},
             "speedup_tsdf_vs_hs": hs_ms / ms,
+            "speedup_full_vs_hs": hs_ms / full_ms if full_ms else None,
         }
         log(f"hs 64+64: {hs_ms:.2f} ms/step")
 

@@ -162,6 +162,30 @@ int hs_upsample(const float *t_coarse, const float *f_coarse, const float *t_out
                 int64_t n_rays, int32_t n_coarse, int32_t n_fine, float s, float *t, float *dt,
                 int32_t *ray_id, int32_t *offsets, void *stream);
 
+/* Coarse + fine sampling inside the TSDF bound (the "Ours (full)" rows of the
+ * Sec. 4.5 tables; supplementary Sec. B.2: fine samples drawn from the PDF of
+ * the coarse samples by the inverse CDF; the coarse/fine scheme of Sec. 2.2).
+ * The adaptive samples of place_samples are each ray's coarse set: ray r owns
+ * positions t_c[offsets_c[r] .. offsets_c[r+1]) (ascending, device), their
+ * section lengths dt_c and SDF values f_c (sdf_mlp_fwd at t_c).  A ray with
+ * n >= 2 coarse points (at most 64 are used: longer sets are cut to their
+ * first 64) gains n_fine fine points, drawn exactly as in hs_upsample from
+ * the NeuS opacity of its n - 1 coarse intervals (weights + 1e-5, quantiles
+ * (m + 1/2)/n_fine, each fine point kept inside its interval); the merged
+ * points y_0 < .. < y_{n+n_fine-1} become samples at the midpoints of the
+ * sections [y_i, y_{i+1}], the last ending at t_f[r].  A ray with n < 2 keeps
+ * its coarse samples (t, dt copied).  Outputs (device, ray order): offsets
+ * [n_rays + 1] (int32), t, dt, ray_id (room for s_cap samples; samples past
+ * s_cap are dropped and the caller checks *s_total_dev, the int64 total).
+ * n_fine in [1, 64]; n_rays * (64 + n_fine) < 2^31.  ws (device):
+ * place_fine_samples_ws_bytes.  Asynchronous on `stream`; no allocation. */
+int place_fine_samples_ws_bytes(int64_t n_rays, size_t *bytes);
+int place_fine_samples(const int32_t *offsets_c, const float *t_c, const float *dt_c,
+                       const float *f_c, const float *t_f, int64_t n_rays, int32_t n_fine,
+                       float s, int32_t *offsets, float *t, float *dt, int32_t *ray_id,
+                       int64_t s_cap, int64_t *s_total_dev, void *ws, size_t ws_bytes,
+                       void *stream);
+
 /* ---------------------------------------------------------------------------
  * Neural field (network of Sec. 3.1, Eq. 1; normal of the supplementary
  * "Normal Estimation").  SDF network: x_hat = (p - center)/scale, positional

@@ -238,6 +238,136 @@ __global__ void __launch_bounds__(256) k_hs_upsample(const float *__restrict__ z
     if (r == n_rays - 1 && lane == 0) offsets[n_rays] = (int32_t)(n_rays * 2 * N);
 }
 
+// ------------------------------------------ coarse + fine inside the bound ----
+// A ray's adaptive samples are its coarse set (at most kFineMaxCoarse are
+// used); a ray with n >= 2 of them gains n_fine fine points.
+
+constexpr int kFineMaxCoarse = 64;
+
+__device__ __forceinline__ int fine_count(const int32_t *off_c, int64_t r, int n_fine, int *n_out) {
+    int n = off_c[r + 1] - off_c[r];
+    n = n < kFineMaxCoarse ? n : kFineMaxCoarse;
+    *n_out = n;
+    return n >= 2 ? n + n_fine : n;
+}
+
+// Per-block totals of the new counts; each ray's offset within its block is
+// parked in offsets[r] for k_fine_sample, which turns it into the global one.
+__global__ void __launch_bounds__(kPlaceBlock) k_fine_count(const int32_t *__restrict__ off_c,
+                                                            int64_t n_rays, int n_fine,
+                                                            int32_t *__restrict__ offsets,
+                                                            int64_t *__restrict__ block_sum) {
+    __shared__ int lds4[4];
+    const int64_t r = blockIdx.x * (int64_t)kPlaceBlock + threadIdx.x;
+    int m = 0, n;
+    if (r < n_rays) m = fine_count(off_c, r, n_fine, &n);
+    int tot;
+    const int ex = block_excl_scan(m, lds4, &tot);
+    if (r < n_rays) offsets[r] = ex;
+    if (threadIdx.x == 0) block_sum[blockIdx.x] = tot;
+}
+
+// One wave per ray.  Coarse points z_k (one per lane) with SDF f_k: NeuS
+// opacity of the n-1 intervals [z_k, z_k+1], weights w_k = T_k alpha_k + 1e-5,
+// probabilities w / sum w; fine point m at the quantile (m + 1/2)/n_fine of
+// that piecewise-uniform density (clamped inside its interval, so the fine
+// points ascend); both sorted lists merged by rank (coarse first on ties);
+// samples at the midpoints of the sections [y_i, y_i+1], the last ending at
+// t_f.  Rays with n < 2 copy their coarse samples.
+__global__ void __launch_bounds__(256) k_fine_sample(const int32_t *__restrict__ off_c,
+                                                     const float *__restrict__ t_c,
+                                                     const float *__restrict__ dt_c,
+                                                     const float *__restrict__ f_c,
+                                                     const float *__restrict__ t_f,
+                                                     int64_t n_rays, int n_fine, float s,
+                                                     const int64_t *__restrict__ block_off,
+                                                     int32_t *__restrict__ offsets,
+                                                     float *__restrict__ t, float *__restrict__ dt,
+                                                     int32_t *__restrict__ ray_id, int64_t s_cap) {
+    constexpr int N = kFineMaxCoarse;
+    __shared__ float s_z[4][N], s_cdf[4][N], s_pdf[4][N], s_y[4][N], s_m[4][2 * N];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int64_t r = blockIdx.x * 4 + wv;
+    const bool valid = r < n_rays;      // no early exit: the block synchronises
+    int n = 0, M = 0;
+    int64_t a = 0, base = 0;
+    if (valid) {
+        M = fine_count(off_c, r, n_fine, &n);
+        a = off_c[r];
+        base = block_off[r / kPlaceBlock] + offsets[r];
+    }
+    const bool up = n >= 2;
+    float z = lane < n ? t_c[a + lane] : 0.0f;
+    float f = lane < n ? f_c[a + lane] : 0.0f;
+    const float f_next = __shfl_down(f, 1);
+    // log(1 - alpha_k) = logsig(s f_k+1) - logsig(s f_k), clamped to <= 0
+    const bool iv = lane < n - 1;
+    float L = iv ? fminf(log_sigmoid(s * f_next) - log_sigmoid(s * f), 0.0f) : 0.0f;
+    float T = expf(wave_incl_scan(L) - L);
+    float w = iv ? T * (-expm1f(L)) + 1e-5f : 0.0f;
+    const float sw = wave_sum(w);
+    float pdf = up ? w / sw : 0.0f;
+    s_cdf[wv][lane] = wave_incl_scan(pdf) - pdf;   // cdf[k] = sum_{j<k} pdf_j
+    s_pdf[wv][lane] = pdf;
+    s_z[wv][lane] = z;
+    __syncthreads();
+    // fine point m = lane: last interval k <= n-2 with cdf[k] <= u
+    if (up && lane < n_fine) {
+        const float u = ((float)lane + 0.5f) / (float)n_fine;
+        int lo = 0, hi = n - 2;
+        while (lo < hi) {
+            int mid = (lo + hi + 1) >> 1;
+            if (s_cdf[wv][mid] <= u) lo = mid; else hi = mid - 1;
+        }
+        const float frac = fminf(fmaxf((u - s_cdf[wv][lo]) / s_pdf[wv][lo], 0.0f), 1.0f);
+        const float z0 = s_z[wv][lo], z1 = s_z[wv][lo + 1];
+        s_y[wv][lane] = z0 + frac * (z1 - z0);
+    }
+    __syncthreads();
+    // merge by rank: coarse i -> i + #(fine < z_i); fine m -> m + #(coarse <= y_m)
+    if (up) {
+        if (lane < n) {
+            int lo = 0, hi = n_fine;            // first fine index with y >= z
+            while (lo < hi) {
+                int mid = (lo + hi) >> 1;
+                if (s_y[wv][mid] < z) lo = mid + 1; else hi = mid;
+            }
+            s_m[wv][lane + lo] = z;
+        }
+        if (lane < n_fine) {
+            const float y = s_y[wv][lane];
+            int lo = 0, hi = n;                 // first coarse index with z > y
+            while (lo < hi) {
+                int mid = (lo + hi) >> 1;
+                if (s_z[wv][mid] <= y) lo = mid + 1; else hi = mid;
+            }
+            s_m[wv][lane + lo] = y;
+        }
+    }
+    __syncthreads();
+    if (!valid) return;
+    if (lane == 0) offsets[r] = (int32_t)base;
+    if (!up) {
+        if (lane < n && base + lane < s_cap) {
+            t[base + lane] = z;
+            dt[base + lane] = dt_c[a + lane];
+            ray_id[base + lane] = (int32_t)r;
+        }
+        return;
+    }
+    const float tend = t_f[r];
+    for (int i = lane; i < M; i += 64) {
+        const float y = s_m[wv][i];
+        const float e = i + 1 < M ? s_m[wv][i + 1] : tend;
+        const int64_t o = base + i;
+        if (o < s_cap) {
+            t[o] = 0.5f * (y + e);
+            dt[o] = e - y;
+            ray_id[o] = (int32_t)r;
+        }
+    }
+}
+
 static unsigned blocks_for(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
 
 }  // namespace tsdfs
@@ -323,6 +453,44 @@ int hs_upsample(const float *t_coarse, const float *f_coarse, const float *t_out
     hipLaunchKernelGGL(k_hs_upsample, dim3(blocks_for(n_rays, 4)), dim3(256), 0,
                        as_stream(stream), t_coarse, f_coarse, t_out, n_rays, s, t, dt, ray_id,
                        offsets);
+    TSDFS_LAUNCH_CHECK();
+    return TSDFS_OK;
+}
+
+int place_fine_samples_ws_bytes(int64_t n_rays, size_t *bytes) {
+    return place_samples_ws_bytes(n_rays, bytes);
+}
+
+int place_fine_samples(const int32_t *offsets_c, const float *t_c, const float *dt_c,
+                       const float *f_c, const float *t_f, int64_t n_rays, int32_t n_fine,
+                       float s, int32_t *offsets, float *t, float *dt, int32_t *ray_id,
+                       int64_t s_cap, int64_t *s_total_dev, void *ws, size_t ws_bytes,
+                       void *stream) {
+    TSDFS_CHECK_ARG(n_rays >= 0, "n_rays must be >= 0");
+    TSDFS_CHECK_ARG(n_fine >= 1 && n_fine <= 64, "need 1 <= n_fine <= 64");
+    TSDFS_CHECK_ARG(n_rays * (int64_t)(kFineMaxCoarse + n_fine) < ((int64_t)1 << 31),
+                    "n_rays * (64 + n_fine) must be < 2^31");
+    TSDFS_CHECK_ARG(s_cap >= 0, "s_cap must be >= 0");
+    TSDFS_CHECK_ARG(offsets && s_total_dev, "NULL array argument");
+    TSDFS_CHECK_ARG(s_cap == 0 || (t && dt && ray_id), "NULL sample array");
+    size_t need;
+    place_samples_ws_bytes(n_rays, &need);
+    TSDFS_CHECK_ARG(ws && ws_bytes >= need, "workspace too small (%zu < %zu)", ws_bytes, need);
+    hipStream_t st = as_stream(stream);
+    int64_t nb = (n_rays + kPlaceBlock - 1) / kPlaceBlock;
+    int64_t *block_sum = (int64_t *)ws;
+    int64_t *block_off = block_sum + nb;
+    if (n_rays > 0) {
+        TSDFS_CHECK_ARG(offsets_c && t_c && dt_c && f_c && t_f, "NULL array argument");
+        hipLaunchKernelGGL(k_fine_count, dim3(nb), dim3(kPlaceBlock), 0, st, offsets_c, n_rays,
+                           n_fine, offsets, block_sum);
+    }
+    hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(1024), 0, st, block_sum, nb, block_off,
+                       s_total_dev, offsets, n_rays);
+    if (n_rays > 0)
+        hipLaunchKernelGGL(k_fine_sample, dim3(blocks_for(n_rays, 4)), dim3(256), 0, st, offsets_c,
+                           t_c, dt_c, f_c, t_f, n_rays, n_fine, s, block_off, offsets, t, dt,
+                           ray_id, s_cap);
     TSDFS_LAUNCH_CHECK();
     return TSDFS_OK;
 }

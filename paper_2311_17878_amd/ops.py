@@ -134,6 +134,37 @@ def place(bounds, rho_num, rho_den, n_min, n_max, s_cap=None, sync=True, ws=None
     return out
 
 
+def place_fine(place, f_coarse, t_f, n_fine, s, s_cap=None, sync=True, ws=None):
+    """Coarse + fine inside the TSDF bound: `place` is the adaptive placement
+    (its samples are the coarse sets), f_coarse the SDF at them.  With
+    sync=True the total is read back, checked against s_cap and the arrays
+    trimmed; otherwise arrays of s_cap come back with the device total."""
+    R = t_f.shape[0]
+    d = _dev()
+    if s_cap is None:
+        s_cap = int(place["t"].shape[0]) + R * int(n_fine)
+    offsets = torch.empty(R + 1, dtype=torch.int32, device=d)
+    t = torch.empty(max(s_cap, 1), dtype=torch.float32, device=d)
+    dt = torch.empty(max(s_cap, 1), dtype=torch.float32, device=d)
+    ray_id = torch.empty(max(s_cap, 1), dtype=torch.int32, device=d)
+    s_total = torch.zeros(1, dtype=torch.int64, device=d)
+    if ws is None:
+        b = ctypes.c_size_t(0)
+        L.check(L.load().place_fine_samples_ws_bytes(R, ctypes.byref(b)))
+        ws = torch.empty(max(b.value, 8), dtype=torch.uint8, device=d)
+    L.check(L.load().place_fine_samples(_p(place["offsets"]), _p(place["t"]), _p(place["dt"]),
+                                        _p(f_coarse), _p(t_f), R, int(n_fine), float(s),
+                                        _p(offsets), _p(t), _p(dt), _p(ray_id), s_cap,
+                                        _p(s_total), _p(ws), ws.numel(), _stream()))
+    out = dict(offsets=offsets, t=t, dt=dt, ray_id=ray_id, s_total=s_total)
+    if sync:
+        S = int(s_total.item())
+        if S > s_cap:
+            raise RuntimeError("place_fine: %d samples exceed s_cap = %d" % (S, s_cap))
+        out.update(t=t[:S], dt=dt[:S], ray_id=ray_id[:S], S=S)
+    return out
+
+
 def hs_coarse(t_in, t_out, n_coarse=64):
     R = t_in.shape[0]
     t = torch.empty(R * n_coarse, dtype=torch.float32, device=_dev())

@@ -84,6 +84,38 @@ class TsdfRenderer:
         out["s_total"] = p["s_total"]
         return out
 
+    def render_full(self, o, v, n_fine, sync=False, keep=False, events=None):
+        """Coarse + fine inside the TSDF bound ("Ours (full)"): Alg. 1 bounds
+        -> adaptive placement (the coarse sets) -> SDF at the coarse samples ->
+        n_fine fine points per ray from the coarse weights -> field at the
+        merged sections -> compositing.  No host synchronisation unless
+        sync=True."""
+        mark = _Marks(events)
+        mark("bounds")
+        b = ops.ray_bounds(self.grid, self.flags, o, v, self.t_far)
+        mark("place")
+        R = o.shape[0]
+        pc = ops.place(b, self.rho[0], self.rho[1], self.n_min, self.n_max, s_cap=R * self.n_max,
+                       sync=sync)
+        mark("field_coarse")
+        fc, _, _ = self.field.forward(o, v, pc["t"], pc["ray_id"],
+                                      s_count=None if sync else pc["s_total"],
+                                      precision=self.precision, full=False, s_cap=pc["t"].shape[0])
+        mark("upsample")
+        cap = R * (min(self.n_max, 64) + int(n_fine))
+        p = ops.place_fine(pc, fc, b["t_f"], n_fine, self.s, s_cap=cap, sync=sync)
+        mark("field")
+        f, g, rgb = self.field.forward(o, v, p["t"], p["ray_id"],
+                                       s_count=None if sync else p["s_total"],
+                                       precision=self.precision, s_cap=p["t"].shape[0])
+        mark("composite")
+        out = ops.composite(p["offsets"], v, p["t"], p["dt"], f, g, rgb, self.s)
+        mark(None)
+        if keep:
+            out.update(bounds=b, coarse=pc, f_coarse=fc, place=p, f=f, grad=g, rgb_s=rgb)
+        out["s_total"] = p["s_total"]
+        return out
+
     def render_hs(self, o, v, keep=False, events=None):
         mark = _Marks(events)
         mark("range+coarse")
