@@ -16,6 +16,12 @@ sampling paragraph: normalised coarse weights), and the merged points are
 rendered.  full_upsample applies the baseline's hs_upsample / hs_sections to
 each ray's own coarse set.
 
+Recovery (Sec. 3.3, last paragraph; Sec. 4.6; supplementary Sec. B.3): a
+ray whose weights in the bound sum to less than tau is rendered again over
+its initial (whole-grid) range with the conventional sampler, here the 64+64
+hierarchical baseline; recover_select gives those rays, recover_merge puts
+their new outputs in place.
+
 Opacity from the SDF ("density transformed from SDF", below Eq. 1): the NeuS
 discrete opacity of a section [t - dt/2, t + dt/2],
 alpha = max((Phi(f_prev) - Phi(f_next)) / Phi(f_prev), 0),  Phi(x) = sigmoid(s x),
@@ -180,3 +186,19 @@ def full_upsample(offsets, t_c, dt_c, f_c, t_f, s, n_fine):
     off = np.concatenate([[0], np.cumsum(counts)])
     cat = lambda x: np.concatenate(x) if x else np.zeros(0)
     return counts, off, cat(ts), cat(dts), cat(rids).astype(np.int64)
+
+
+def recover_select(acc, tau):
+    """Rays to recover, ascending: those whose weight sum is not >= tau
+    (NaN included)."""
+    acc = np.asarray(acc, np.float64)
+    return np.flatnonzero(~(acc >= tau))
+
+
+def recover_merge(out, idx, sub):
+    """Copy of the render outputs `out` (dict of per-ray arrays) with rows idx
+    replaced by the recovered rays' outputs `sub` (same keys, len(idx) rows)."""
+    res = {k: np.array(v, copy=True) for k, v in out.items()}
+    for k in res:
+        res[k][idx] = sub[k]
+    return res

@@ -213,3 +213,19 @@ def test_full_upsample_concentrates_at_the_crossing():
     fine = np.setdiff1d(np.round(edges[:-1], 12), np.round(z, 12))
     assert fine.size == n_fine
     assert np.median(fine) == pytest.approx(2.3, abs=0.25)
+
+
+def test_recover_select_and_merge_by_hand():
+    """Selection is strict (acc == tau stays), takes NaN, keeps ray order;
+    the merge replaces exactly the selected rows."""
+    acc = np.array([1.0, 0.95, 0.9499999, 0.0, np.nan, 0.2, 0.99])
+    idx = Rn.recover_select(acc, 0.95)
+    assert idx.tolist() == [2, 3, 4, 5]
+    assert Rn.recover_select(np.zeros(0), 0.95).size == 0
+    out = {"acc": acc.copy(), "rgb": np.arange(21.0).reshape(7, 3)}
+    sub = {"acc": np.array([0.5, 0.6, 0.7, 0.8]), "rgb": -np.ones((4, 3))}
+    m = Rn.recover_merge(out, idx, sub)
+    assert m["acc"].tolist()[:2] == [1.0, 0.95] and m["acc"][6] == 0.99
+    assert m["acc"][idx].tolist() == [0.5, 0.6, 0.7, 0.8]
+    assert (m["rgb"][idx] == -1).all() and (m["rgb"][[0, 1, 6]] == out["rgb"][[0, 1, 6]]).all()
+    assert np.isnan(out["acc"][4])            # the input is untouched
