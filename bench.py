@@ -124,6 +124,8 @@ def main():
     ap.add_argument("--no-hs", action="store_true")
     ap.add_argument("--no-other", action="store_true", help="skip the other-precision leg")
     ap.add_argument("--no-train", action="store_true", help="skip the training-step leg")
+    ap.add_argument("--recover-tau", type=float, default=0.95,
+                    help="weight-sum threshold of the recovery leg (0: skip the leg)")
     ap.add_argument("--full-fine", type=int, default=8,
                     help="fine samples per ray of the coarse + fine leg (0: skip the leg)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -328,6 +330,30 @@ def main():
                          for k, v_ in ev_f.items()},
         }
         log(f"full (+{nf} fine): {full_ms:.3f} ms/step, {S_f / n_rays:.2f} rendered samples/ray")
+
+    # ---- recovery: bounded render, then rays with weight sum < tau rendered
+    # again over their initial range by the 64+64 hierarchical sampler
+    if args.recover_tau > 0:
+        tau = args.recover_tau
+        for _ in range(args.warmup):
+            R.render_recover(ro_d, rv_d, tau)
+        ev_r = {}
+        torch.cuda.synchronize()
+        start.record()
+        for _ in range(args.steps):
+            out_r = R.render_recover(ro_d, rv_d, tau, events=ev_r)
+        end.record()
+        torch.cuda.synchronize()
+        rec_ms = start.elapsed_time(end) / args.steps
+        n_rec = int(out_r["n_recovered"])
+        result["recover"] = {
+            "tau": tau, "ms_per_step": rec_ms, "rays_per_s": n_rays / (rec_ms * 1e-3),
+            "rays_recovered": n_rec, "frac_recovered": n_rec / n_rays,
+            "samples_per_ray_total": (S + 192 * n_rec) / n_rays,
+            "stage_ms": {k: float(np.mean([a.elapsed_time(b) for a, b in v_]))
+                         for k, v_ in ev_r.items()},
+        }
+        log(f"recover (tau {tau}): {rec_ms:.3f} ms/step, {n_rec} rays recovered")
 
     # ---- one TSDF-bounded training step (8192 rays + 8192 eikonal points)
     if cfg.name in ("c2", "c3", "c4") and not args.no_train:

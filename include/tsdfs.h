@@ -186,6 +186,26 @@ int place_fine_samples(const int32_t *offsets_c, const float *t_c, const float *
                        int64_t s_cap, int64_t *s_total_dev, void *ws, size_t ws_bytes,
                        void *stream);
 
+/* Recovery (Sec. 3.3, last paragraph; Sec. 4.6; supplementary Sec. B.3): a
+ * ray whose weights in its bound sum to less than tau is rendered again over
+ * its initial range with the conventional sampler.
+ * select_rays: idx[0 .. n) = the rays r with !(acc[r] >= tau) (NaN included),
+ * ascending; n is written to *n_sel_dev (int64, device).  acc [n_rays] and idx
+ * (room for n_rays) on the device.  ws: select_rays_ws_bytes.
+ * gather_rays: o_sub[i] = o[idx[i]], v_sub[i] = v[idx[i]] ([.., 3] float) for
+ * i < min(*n_sel_dev, cap).
+ * scatter_rays: rgb[idx[i]] = rgb_sub[i] (3 floats), depth, normal (3), acc
+ * likewise, for i < min(*n_sel_dev, cap); other rays are left untouched.
+ * All asynchronous on `stream`; no allocation. */
+int select_rays_ws_bytes(int64_t n_rays, size_t *bytes);
+int select_rays(const float *acc, int64_t n_rays, float tau, int32_t *idx, int64_t *n_sel_dev,
+                void *ws, size_t ws_bytes, void *stream);
+int gather_rays(const int32_t *idx, const int64_t *n_sel_dev, int64_t cap, const float *o,
+                const float *v, float *o_sub, float *v_sub, void *stream);
+int scatter_rays(const int32_t *idx, const int64_t *n_sel_dev, int64_t cap, const float *rgb_sub,
+                 const float *depth_sub, const float *normal_sub, const float *acc_sub, float *rgb,
+                 float *depth, float *normal, float *acc, void *stream);
+
 /* ---------------------------------------------------------------------------
  * Neural field (network of Sec. 3.1, Eq. 1; normal of the supplementary
  * "Normal Estimation").  SDF network: x_hat = (p - center)/scale, positional

@@ -165,6 +165,38 @@ def place_fine(place, f_coarse, t_f, n_fine, s, s_cap=None, sync=True, ws=None):
     return out
 
 
+def select_rays(acc, tau):
+    """Rays to recover (weight sum not >= tau), ascending; returns the index
+    array (room for every ray) and the device count."""
+    R = acc.shape[0]
+    d = _dev()
+    idx = torch.empty(max(R, 1), dtype=torch.int32, device=d)
+    n_sel = torch.zeros(1, dtype=torch.int64, device=d)
+    b = ctypes.c_size_t(0)
+    L.check(L.load().select_rays_ws_bytes(R, ctypes.byref(b)))
+    ws = torch.empty(max(b.value, 8), dtype=torch.uint8, device=d)
+    L.check(L.load().select_rays(_p(acc), R, float(tau), _p(idx), _p(n_sel), _p(ws), ws.numel(),
+                                 _stream()))
+    return idx, n_sel
+
+
+def gather_rays(idx, n_sel, o, v, cap):
+    d = _dev()
+    o_sub = torch.empty((max(cap, 1), 3), dtype=torch.float32, device=d)
+    v_sub = torch.empty((max(cap, 1), 3), dtype=torch.float32, device=d)
+    L.check(L.load().gather_rays(_p(idx), _p(n_sel), cap, _p(o), _p(v), _p(o_sub), _p(v_sub),
+                                 _stream()))
+    return o_sub[:cap], v_sub[:cap]
+
+
+def scatter_rays(idx, n_sel, cap, sub, out):
+    """out[k][idx[i]] = sub[k][i] for rgb, depth, normal, acc (in place)."""
+    L.check(L.load().scatter_rays(_p(idx), _p(n_sel), cap, _p(sub["rgb"]), _p(sub["depth"]),
+                                  _p(sub["normal"]), _p(sub["acc"]), _p(out["rgb"]),
+                                  _p(out["depth"]), _p(out["normal"]), _p(out["acc"]), _stream()))
+    return out
+
+
 def hs_coarse(t_in, t_out, n_coarse=64):
     R = t_in.shape[0]
     t = torch.empty(R * n_coarse, dtype=torch.float32, device=_dev())

@@ -116,6 +116,29 @@ class TsdfRenderer:
         out["s_total"] = p["s_total"]
         return out
 
+    def render_recover(self, o, v, tau=0.95, n_fine=0, keep=False, events=None):
+        """TSDF-bounded render (with n_fine fine samples per ray when > 0),
+        then recovery: rays whose weights sum to less than tau are rendered
+        again over their initial range with the 64+64 hierarchical sampler
+        and their outputs replace the bounded ones.  One host
+        synchronisation (the number of recovered rays sizes the re-render)."""
+        mark = _Marks(events)
+        out = self.render_full(o, v, n_fine) if n_fine > 0 else self.render(o, v)
+        mark("select")
+        idx, n_sel = ops.select_rays(out["acc"], tau)
+        n = int(n_sel.item())
+        out["n_recovered"] = n
+        if n > 0:
+            mark("gather")
+            o_s, v_s = ops.gather_rays(idx, n_sel, o, v, n)
+            rec = self.render_hs(o_s, v_s)
+            mark("scatter")
+            ops.scatter_rays(idx, n_sel, n, rec, out)
+        mark(None)
+        if keep:
+            out.update(recovered=idx[:n])
+        return out
+
     def render_hs(self, o, v, keep=False, events=None):
         mark = _Marks(events)
         mark("range+coarse")
