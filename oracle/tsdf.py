@@ -181,3 +181,28 @@ def place(t_n, t_f, n_vox, status, rho_num, rho_den, n_min, n_max):
     dt = (tf - tn) / counts[ray_id]
     t = tn + (k + 0.5) * dt
     return dict(counts=counts, offsets=offsets, t=t, dt=dt, ray_id=ray_id)
+
+
+LEN_Q = float(1 << 24)   # fixed-point unit of the summed lengths: 2^-24 m
+
+
+def containment(t_in, t_out, b, depth):
+    """The counting of Table 1 (Sec. 4.3) over the rays that carry an
+    integration depth: how many, how many fail (status not HIT / NO_FAR, or
+    the depth outside [t_n, t_f]), and the summed original range t_out - t_in
+    (the ray's span of the grid) and reduced range t_f - t_n (zero for rays
+    without a bound).  Lengths are the FP32 differences, summed exactly in
+    units of 2^-24 m (round half to even), so that any summation order gives
+    the same integers.
+    """
+    depth = np.asarray(depth, np.float32)
+    hit = np.isfinite(depth)
+    st = b["status"]
+    ok = (st == ST_HIT) | (st == ST_NO_FAR)
+    t_n, t_f = np.float32(b["t_n"]), np.float32(b["t_f"])
+    inside = ok & (t_n <= depth) & (depth <= t_f)
+    orig = np.float32(t_out) - np.float32(t_in)
+    red = np.where(ok, t_f - t_n, np.float32(0.0)).astype(np.float32)
+    q = lambda x: int(np.rint(x[hit].astype(np.float64) * LEN_Q).astype(np.int64).sum())
+    return dict(rays=int(hit.sum()), failed=int((hit & ~inside).sum()),
+                original_q=q(orig), reduced_q=q(red))

@@ -19,7 +19,7 @@ import numpy as np
 from .scenes import Scene, Sphere, Box, Room, pinhole_rays, equirect_rays, ray_depth, shade
 from .weights import SdfNet, ColorNet, sdf_params, color_params
 
-CONFIG_NAMES = ("c1", "c2", "c3", "c4", "c5")
+CONFIG_NAMES = ("c1", "c2", "c3", "c4", "c5", "c1n", "c2n")
 
 
 @dataclass(frozen=True)
@@ -65,6 +65,11 @@ class Config:
     integ_views: object = None      # callable(scene) -> list of (o, v) per view
     render_view: object = None      # callable(scene) -> (o, v)
     notes: str = ""
+    # depth of a density field (NeRF-like) instead of the exact surface
+    # distance: per view, seeded Gaussian error of sigma_vox voxels on every
+    # ray and, on a fraction `floaters` of the rays, a spurious hit uniformly
+    # between 30% and 100% of the true depth (None: exact depths)
+    depth_noise: tuple = None       # (sigma_vox, floaters)
 
     # -- cached products -------------------------------------------------
     _scene: object = field(default=None, repr=False)
@@ -83,8 +88,22 @@ class Config:
         workers = max(1, min(16, os.cpu_count() or 1, len(vs)))
         with ThreadPoolExecutor(workers) as ex:
             ds_ = list(ex.map(lambda ov: ray_depth(sc, ov[0], ov[1]), vs))
+        if self.depth_noise is not None:
+            ids = range(len(vs)) if views is None else views
+            ds_ = [self._noisy(d, i) for d, i in zip(ds_, ids)]
         return (np.concatenate([o for o, _ in vs]), np.concatenate([v for _, v in vs]),
                 np.concatenate(ds_))
+
+    def _noisy(self, d, view):
+        sigma_vox, floaters = self.depth_noise
+        rng = np.random.Generator(np.random.PCG64(1000 + view))
+        d64 = d.astype(np.float64)
+        e = rng.normal(0.0, sigma_vox * self.grid.h, d.shape)
+        fl = rng.uniform(size=d.shape) < floaters
+        spur = rng.uniform(0.3, 1.0, d.shape) * d64
+        out = np.where(fl, spur, d64 + e)
+        out = np.where(np.isfinite(d64), np.maximum(out, 1e-3), d64)
+        return out.astype(np.float32)
 
     def render_rays(self):
         o, v = self.render_view(self.scene())
@@ -280,8 +299,22 @@ def _c5():
     )
 
 
+def _nerf_mode(cfg, name):
+    """The same scene and views fused from density-field-like depths with
+    the bound parameters used for NeRF: D_T = 39h, D_s = 27h, 7^3
+    neighbourhood, M = 15."""
+    g = cfg.grid
+    return replace(cfg, name=name, grid=replace(g, d_t=39 * g.h, d_s=27 * g.h, nb_radius=3),
+                   depth_noise=(2.0, 0.01),
+                   notes=cfg.notes + "; NeRF-mode bounds on noisy depths (sigma 2h, 1% floaters)")
+
+
 def get_config(name: str) -> Config:
     name = name.lower()
+    if name == "c1n":
+        return _nerf_mode(_c1(), "c1n")
+    if name == "c2n":
+        return _nerf_mode(_c2(), "c2n")
     if name == "c1":
         return _c1()
     if name == "c2":

@@ -307,3 +307,18 @@ def test_placement_invariants():
     # naive variant: a fixed count per ray
     q = tsdf.place(t_n, t_f, n_vox, status, 1, 1, 6, 6)
     assert (q["counts"][ok] == 6).all()
+
+
+def test_containment_counting_by_hand():
+    """Table 1's counting on hand-made rays: statuses, a depth on each bound
+    (inside), just past them (failures), rays without depth ignored, lengths
+    summed in 2^-24 m units."""
+    st = np.array([0, 1, 0, 0, 2, 3, 0], np.uint8)
+    b = dict(status=st, t_n=np.float32([1, 1, 1, 1, 0, 0, 2]), t_f=np.float32([2, 5, 2, 2, 0, 0, 3]))
+    depth = np.float32([1.0, 5.0, np.nextafter(np.float32(2), np.float32(3)), 1.5, 1.0, 1.0, np.inf])
+    t_in = np.float32([0.5] * 7)
+    t_out = np.float32([4.5] * 7)
+    c = tsdf.containment(t_in, t_out, b, depth)
+    assert c["rays"] == 6 and c["failed"] == 3          # the 2.0000002, MISS and INVALID rays
+    assert c["original_q"] == 6 * 4 * (1 << 24)
+    assert c["reduced_q"] == (1 + 4 + 1 + 1) * (1 << 24)
