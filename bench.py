@@ -124,6 +124,8 @@ def main():
     ap.add_argument("--no-hs", action="store_true")
     ap.add_argument("--no-other", action="store_true", help="skip the other-precision leg")
     ap.add_argument("--no-train", action="store_true", help="skip the training-step leg")
+    ap.add_argument("--no-table1", action="store_true",
+                    help="skip Table 1's counting on the training rays and the NeRF-mode leg")
     ap.add_argument("--recover-tau", type=float, default=0.95,
                     help="weight-sum threshold of the recovery leg (0: skip the leg)")
     ap.add_argument("--full-fine", type=int, default=8,
@@ -330,6 +332,62 @@ def main():
                          for k, v_ in ev_f.items()},
         }
         log(f"full (+{nf} fine): {full_ms:.3f} ms/step, {S_f / n_rays:.2f} rendered samples/ray")
+
+    # ---- Table 1's counting on the training rays (this workload's bounds),
+    # then the same scene fused from density-field-like depths in NeRF mode
+    # (D_T = 39h, D_s = 27h, 7^3 neighbourhood): counting, integration and
+    # a render of the view with those bounds
+    def table1(rr, o_, v_, d_):
+        bt = ops.ray_bounds(rr.grid, rr.flags, o_, v_, rr.t_far)
+        ti, to = ops.ray_range(rr.grid, o_, v_)
+        c = ops.bound_stats(ti, to, bt, d_).cpu().numpy().tolist()
+        q = float(1 << 24)
+        return {"rays_with_depth": c[0], "failed": c[1], "failed_frac": c[1] / max(c[0], 1),
+                "original_range_m": c[2] / q / max(c[0], 1), "reduced_range_m": c[3] / q / max(c[0], 1)}
+    nerf_name = cfg.name + "n"
+    if not args.no_table1:
+        result["table1"] = {cfg.name: table1(R, o_d, v_d, d_d)}
+        try:
+            cfg_n = get_config(nerf_name)
+        except KeyError:
+            cfg_n = None
+        if cfg_n is not None:
+            gn = cfg_n.grid
+            _, _, dn = cfg_n.integration_rays()
+            dn_d = dev(dn)
+            grid_n = ops.make_grid(gn.n, gn.lo, gn.h, gn.d_t, gn.d_s, gn.nb_radius, gn.m_consec)
+            Rn = TsdfRenderer(grid_n, field, s.rho_num, s.rho_den, s.n_min, s.n_max, cfg.neus_s,
+                              s.t_far, prec)
+            nup_n = torch.zeros(1, dtype=torch.int64, device="cuda")
+            Rn.state = ops.new_state(grid_n)
+            torch.cuda.synchronize()
+            e0.record()
+            Rn.integrate(o_d, v_d, dn_d, batch=o.shape[0], n_updates=nup_n)
+            e1.record()
+            torch.cuda.synchronize()
+            integ_n = e0.elapsed_time(e1)
+            Rn.finalize()
+            t1n = table1(Rn, o_d, v_d, dn_d)
+            for _ in range(args.warmup):
+                Rn.render(ro_d, rv_d)
+            torch.cuda.synchronize()
+            start.record()
+            for _ in range(args.steps):
+                out_n = Rn.render(ro_d, rv_d)
+            end.record()
+            torch.cuda.synchronize()
+            ms_n = start.elapsed_time(end) / args.steps
+            S_n = int(out_n["s_total"].item())
+            t1n.update({"integrate_ms": integ_n, "voxel_updates": int(nup_n.item()),
+                        "render_ms_per_step": ms_n, "render_rays_per_s": n_rays / (ms_n * 1e-3),
+                        "samples_per_ray": S_n / n_rays,
+                        "bounds": f"D_T={gn.d_t / gn.h:g}h, D_s={gn.d_s / gn.h:g}h, "
+                                  f"{2 * gn.nb_radius + 1}^3, M={gn.m_consec}",
+                        "depths": "exact depths plus seeded N(0, (2h)^2) error, 1% floaters "
+                                  "uniform in [0.3, 1] x depth"})
+            result["table1"][nerf_name] = t1n
+            log(f"table1 {cfg.name}: {result['table1'][cfg.name]}; {nerf_name}: {t1n}")
+            del Rn, dn_d
 
     # ---- recovery: bounded render, then rays with weight sum < tau rendered
     # again over their initial range by the 64+64 hierarchical sampler

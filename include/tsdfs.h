@@ -125,6 +125,18 @@ int tsdf_ray_bounds(const tsdfs_grid *grid, const uint8_t *flags, const float *o
 int tsdf_ray_range(const tsdfs_grid *grid, const float *o, const float *v, int64_t n_rays,
                    float *t_in, float *t_out, void *stream);
 
+/* The counting of Table 1 (Sec. 4.3) over the rays that carry an integration
+ * depth (finite depth[r]): out[0] = such rays, out[1] = failures (status not
+ * HIT / NO_FAR, or depth outside [t_n, t_f]), out[2] = sum of the original
+ * ranges t_out - t_in (tsdf_ray_range), out[3] = sum of the reduced ranges
+ * t_f - t_n (0 for rays without a bound), both in units of 2^-24 m (each
+ * FP32 length times 2^24 rounded to nearest even, summed exactly in int64).
+ * All arrays [n_rays] on the device; out: 4 int64 on the device, cleared
+ * by the call.  Asynchronous on `stream`. */
+int tsdf_bound_stats(const float *t_in, const float *t_out, const float *t_n, const float *t_f,
+                     const uint8_t *status, const float *depth, int64_t n_rays, int64_t *out,
+                     void *stream);
+
 /* ---------------------------------------------------------------------------
  * Adaptive sample placement (Sec. 3.4): n_i = clamp(ceil(n_vox rho_num /
  * rho_den), n_min, n_max) for HIT / NO_FAR rays, 0 otherwise (n_min = n_max

@@ -50,6 +50,7 @@ SIGNATURES = {
                       c_int64, P, P, P, c_size_t, P],
     "hs_coarse": [P, P, c_int64, c_int32, P, P, P],
     "hs_upsample": [P, P, P, c_int64, c_int32, c_int32, c_float, P, P, P, P, P],
+    "tsdf_bound_stats": [P, P, P, P, P, P, c_int64, P, P],
     "select_rays_ws_bytes": [c_int64, P],
     "select_rays": [P, c_int64, c_float, P, P, P, c_size_t, P],
     "gather_rays": [P, P, c_int64, P, P, P, P, P],

@@ -261,6 +261,54 @@ __global__ void k_ray_range(LatGrid g, const float *__restrict__ o, const float 
 
 static unsigned blocks_for(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
 
+// Table 1's counting over the rays with an integration depth (finite):
+// out[0] rays, out[1] failures (no bound, or the depth outside [t_n, t_f]),
+// out[2] / out[3] the summed original (t_out - t_in) and reduced (t_f - t_n)
+// lengths in units of 2^-24 m (each FP32 length times 2^24, rounded to the
+// nearest integer), so that the int64 sums do not depend on the order.
+__global__ void k_zero_i64(int64_t *__restrict__ p, int n) {
+    if ((int)threadIdx.x < n) p[threadIdx.x] = 0;
+}
+
+__global__ void __launch_bounds__(256) k_bound_stats(const float *__restrict__ t_in,
+                                                     const float *__restrict__ t_out,
+                                                     const float *__restrict__ t_n,
+                                                     const float *__restrict__ t_f,
+                                                     const uint8_t *__restrict__ status,
+                                                     const float *__restrict__ depth,
+                                                     int64_t n_rays,
+                                                     unsigned long long *__restrict__ out) {
+    __shared__ unsigned long long part[4][4];
+    const int64_t r = blockIdx.x * 256LL + threadIdx.x;
+    long long c[4] = {0, 0, 0, 0};
+    if (r < n_rays) {
+        const float d = depth[r];
+        if (isfinite(d)) {
+            const uint8_t st = status[r];
+            const bool ok = st == TSDFS_HIT || st == TSDFS_NO_FAR;
+            const float a = t_n[r], b = t_f[r];
+            c[0] = 1;
+            c[1] = (ok && a <= d && d <= b) ? 0 : 1;
+            c[2] = __float2ll_rn((t_out[r] - t_in[r]) * 16777216.0f);
+            c[3] = ok ? __float2ll_rn((b - a) * 16777216.0f) : 0;
+        }
+    }
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        long long x = c[k];
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off);
+        if (lane == 0) part[wv][k] = (unsigned long long)x;
+    }
+    __syncthreads();
+    if (threadIdx.x < 4) {
+        const unsigned long long s = part[0][threadIdx.x] + part[1][threadIdx.x] +
+                                     part[2][threadIdx.x] + part[3][threadIdx.x];
+        if (s) atomicAdd(out + threadIdx.x, s);
+    }
+}
+
 }  // namespace tsdfs
 
 using namespace tsdfs;
@@ -357,6 +405,24 @@ int tsdf_ray_range(const tsdfs_grid *grid, const float *o, const float *v, int64
     TSDFS_CHECK_ARG(o && v && t_in && t_out, "NULL array argument");
     hipLaunchKernelGGL(k_ray_range, dim3(blocks_for(n_rays, 256)), dim3(256), 0,
                        as_stream(stream), g, o, v, n_rays, t_in, t_out);
+    TSDFS_LAUNCH_CHECK();
+    return TSDFS_OK;
+}
+
+int tsdf_bound_stats(const float *t_in, const float *t_out, const float *t_n, const float *t_f,
+                     const uint8_t *status, const float *depth, int64_t n_rays, int64_t *out,
+                     void *stream) {
+    TSDFS_CHECK_ARG(n_rays >= 0, "n_rays must be >= 0");
+    TSDFS_CHECK_ARG(out, "NULL out");
+    hipStream_t st = as_stream(stream);
+    hipLaunchKernelGGL(k_zero_i64, dim3(1), dim3(64), 0, st, out, 4);
+    if (n_rays == 0) {
+        TSDFS_LAUNCH_CHECK();
+        return TSDFS_OK;
+    }
+    TSDFS_CHECK_ARG(t_in && t_out && t_n && t_f && status && depth, "NULL array argument");
+    hipLaunchKernelGGL(k_bound_stats, dim3((unsigned)((n_rays + 255) / 256)), dim3(256), 0, st, t_in,
+                       t_out, t_n, t_f, status, depth, n_rays, (unsigned long long *)out);
     TSDFS_LAUNCH_CHECK();
     return TSDFS_OK;
 }

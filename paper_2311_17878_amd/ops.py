@@ -165,6 +165,16 @@ def place_fine(place, f_coarse, t_f, n_fine, s, s_cap=None, sync=True, ws=None):
     return out
 
 
+def bound_stats(t_in, t_out, bounds, depth):
+    """Table 1's counting (device int64 [4]: rays with depth, failures, summed
+    original and reduced range in 2^-24 m units)."""
+    out = torch.empty(4, dtype=torch.int64, device=_dev())
+    L.check(L.load().tsdf_bound_stats(_p(t_in), _p(t_out), _p(bounds["t_n"]), _p(bounds["t_f"]),
+                                      _p(bounds["status"]), _p(depth), depth.shape[0], _p(out),
+                                      _stream()))
+    return out
+
+
 def select_rays(acc, tau):
     """Rays to recover (weight sum not >= tau), ascending; returns the index
     array (room for every ray) and the device count."""
