@@ -35,8 +35,8 @@ HBM_PEAK_GBS = 8000.0
 FIELD_SOURCES = {"k_field_fp32": ["field_fp32.hip", "field_common.hpp", "common.hpp", "field.hip"],
                  "k_field_bf16": ["field_bf16.hip", "field_common.hpp", "common.hpp", "field.hip"]}
 TRAFFIC = {
-    "k_field_fp32": {"sha256_16": "580c3d1a41255800", "fetch_kib": 3.383e7, "write_kib": 5.786e7},
-    "k_field_bf16": {"sha256_16": "08274f2344e4a306", "fetch_kib": 2.018e7, "write_kib": 2.088e7},
+    "k_field_fp32": {"sha256_16": "55fcae97004f8465", "fetch_kib": 3.64e+07, "write_kib": 5.785e+07},
+    "k_field_bf16": {"sha256_16": "4574a94cb35825f0", "fetch_kib": 1.92e+07, "write_kib": 2.103e+07},
 }
 COPY_SCALE = {"fetch": 2.0, "write": 1.0}
 
