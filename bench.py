@@ -437,6 +437,36 @@ def main():
                              "bf16 product inputs, f32 accumulation (forward and backward)",
             }
             log(f"{tname}: {tms:.2f} ms")
+        # a multi-step training loop: train_step, Adam over the field's
+        # parameters, repack of the forward operands, on 10 pre-uploaded
+        # batches in turn (a separate field, so the render legs keep theirs)
+        from paper_2311_17878_amd.autograd import train, Adam
+        bl = []
+        for k in range(10):
+            bo, bv, bt = cfg.training_batch(8192, seed=100 + k)
+            bl.append((dev(bo), dev(bv), dev(bt), dev(cfg.eikonal_points(8192, seed=100 + k))))
+        n_loop = max(2, min(args.steps, 10))
+        for lname, lprec in (("train_loop", _lib.FP32), ("train_loop_bf16", _lib.BF16)):
+            fl = ops.Field(cfg.sdf.width, cfg.sdf.n_hidden, cfg.sdf.pe_freqs, cfg.sdf.skip_at,
+                           cfg.sdf.n_feat, cfg.color.n_hidden, cfg.sdf.beta, cfg.in_center,
+                           cfg.in_scale, cfg.sdf_params(), cfg.color_params())
+            saved = R.field
+            R.field = fl
+            opt = Adam(fl, lr=5e-4)
+            train(R, lambda k: bl[k % 10], 1, precision=lprec, opt=opt)       # warm-up
+            torch.cuda.synchronize()
+            start.record()
+            hist, _ = train(R, lambda k: bl[(k + 1) % 10], n_loop, precision=lprec, opt=opt)
+            end.record()
+            torch.cuda.synchronize()
+            R.field = saved
+            lms = start.elapsed_time(end) / n_loop
+            result[lname] = {
+                "steps": n_loop, "ms_per_step": lms, "rays_per_s": 8192 / (lms * 1e-3),
+                "loss_rgb_first": hist[0][0], "loss_rgb_last": hist[-1][0],
+                "optimizer": "Adam lr 5e-4 (device), packed operands rebuilt every step",
+            }
+            log(f"{lname}: {lms:.2f} ms/step, loss {hist[0][0]:.5f} -> {hist[-1][0]:.5f}")
 
     if not args.no_hs:
         for _ in range(1):

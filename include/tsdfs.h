@@ -248,6 +248,23 @@ int tsdfs_field_create(const tsdfs_field_desc *desc, const float *sdf_params_hos
                        const float *color_params_host, tsdfs_field **out);
 int tsdfs_field_destroy(tsdfs_field *field);
 
+/* Parameters of a field for a training loop: *params_dev = the device FP32
+ * plain parameters (the SDF block of *n_sdf floats, then the colour block of
+ * *n_color, in the layouts tsdfs_field_create takes), owned by the field and
+ * updated in place by the caller (e.g. adam_step).  tsdfs_field_repack then
+ * rebuilds the packed copies the forward kernels read (FP32 and BF16 MFMA
+ * operands, bias tiles) from them on `stream`; tsdfs_field_create packs the
+ * same way.  The backward (sdf_mlp_bwd) reads the plain parameters directly. */
+int tsdfs_field_params(tsdfs_field *field, float **params_dev, size_t *n_sdf, size_t *n_color);
+int tsdfs_field_repack(tsdfs_field *field, void *stream);
+
+/* One Adam step (the optimiser of the NeuS-family training the method builds
+ * on) over n device floats: m = b1 m + (1 - b1) g, v = b2 v + (1 - b2) g^2,
+ * params -= lr (m / (1 - b1^step)) / (sqrt(v / (1 - b2^step)) + eps); m, v
+ * start at zero and are owned by the caller; step >= 1 counts the updates. */
+int adam_step(float *params, const float *grad, float *m, float *v, int64_t n, float lr,
+              float beta1, float beta2, float eps, int32_t step, void *stream);
+
 /* Evaluate the field at p = o[ray_id] + t v[ray_id] for min(*s_count_dev,
  * s_cap) samples (s_count_dev may be NULL: s_cap samples).  Outputs [S]:
  * f (metres), grad_f [S,3] and rgb [S,3]; with grad_f == rgb == NULL only f

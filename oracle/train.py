@@ -76,3 +76,15 @@ def loss_value(cfg, sdf_params64, color_params64, batch):
     sl = layers(np.asarray(sdf_params64, np.float64), cfg.sdf.layer_dims())
     cl = layers(np.asarray(color_params64, np.float64), cfg.color.layer_dims())
     return float(loss_t(cfg, sl, cl, batch))
+
+
+def adam(p, g, m, v, lr, beta1, beta2, eps, t):
+    """One Adam update in FP64 (the optimiser of the NeuS-family training
+    the method builds on): returns (p, m, v) after step t >= 1."""
+    p, g, m, v = (np.asarray(x, np.float64) for x in (p, g, m, v))
+    m = beta1 * m + (1.0 - beta1) * g
+    v = beta2 * v + (1.0 - beta2) * g * g
+    mh = m / (1.0 - beta1 ** t)
+    vh = v / (1.0 - beta2 ** t)
+    return p - lr * mh / (np.sqrt(vh) + eps), m, v
+

@@ -51,6 +51,9 @@ SIGNATURES = {
     "hs_coarse": [P, P, c_int64, c_int32, P, P, P],
     "hs_upsample": [P, P, P, c_int64, c_int32, c_int32, c_float, P, P, P, P, P],
     "tsdf_bound_stats": [P, P, P, P, P, P, c_int64, P, P],
+    "tsdfs_field_params": [P, P, P, P],
+    "tsdfs_field_repack": [P, P],
+    "adam_step": [P, P, P, P, c_int64, c_float, c_float, c_float, c_float, c_int32, P],
     "select_rays_ws_bytes": [c_int64, P],
     "select_rays": [P, c_int64, c_float, P, P, P, c_size_t, P],
     "gather_rays": [P, P, c_int64, P, P, P, P, P],

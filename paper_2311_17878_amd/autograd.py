@@ -75,3 +75,44 @@ def train_step(renderer, o, v, target, eik_x, eik_lambda=0.1, precision=FP32):
     d_sdf, d_col, eik = R.field.backward(o, v, p["t"], p["ray_id"], d_f, d_g, d_c,
                                          eik_x=eik_x, eik_lambda=eik_lambda, precision=precision)
     return loss, eik, d_sdf, d_col, p["S"]
+
+
+class Adam:
+    """Adam over a field's plain parameters (SDF block and colour block, one
+    device array), with the packed forward operands rebuilt after each step.
+    The update runs in libtsdfs.so (adam_step, tsdfs_field_repack)."""
+
+    def __init__(self, field, lr=5e-4, betas=(0.9, 0.999), eps=1e-8):
+        self.field = field
+        self.ptr, self.n_sdf, self.n_col = field.params()
+        n = self.n_sdf + self.n_col
+        d = torch.device("cuda")
+        self.m = torch.zeros(n, dtype=torch.float32, device=d)
+        self.v = torch.zeros(n, dtype=torch.float32, device=d)
+        self.lr, self.betas, self.eps = float(lr), betas, float(eps)
+        self.t = 0
+
+    def step(self, d_sdf, d_col):
+        self.t += 1
+        b1, b2 = self.betas
+        ops.adam_step(self.ptr, d_sdf, self.m[:self.n_sdf], self.v[:self.n_sdf], self.lr, b1, b2,
+                      self.eps, self.t)
+        ops.adam_step(self.ptr + 4 * self.n_sdf, d_col, self.m[self.n_sdf:], self.v[self.n_sdf:],
+                      self.lr, b1, b2, self.eps, self.t)
+        self.field.repack()
+
+
+def train(renderer, batches, n_steps, eik_lambda=0.1, precision=FP32, opt=None):
+    """A TSDF-bounded training loop: for each step, batches(step) gives
+    device (o, v, target, eik_x); one train_step, then one Adam update of the
+    field.  Returns the per-step (loss_rgb, loss_eik) as floats and the
+    optimiser."""
+    opt = opt or Adam(renderer.field)
+    hist = []
+    for k in range(n_steps):
+        o, v, target, eik_x = batches(k)
+        loss, eik, d_sdf, d_col, _ = train_step(renderer, o, v, target, eik_x, eik_lambda, precision)
+        opt.step(d_sdf, d_col)
+        hist.append((loss, eik))
+    return [(float(a.item()), float(b.item())) for a, b in hist], opt
+

@@ -11,56 +11,86 @@ namespace tsdfs {
 
 static int round8(int k) { return (k + 7) / 8 * 8; }
 
-// Pack an n_out x K matrix given by m(r, k) as the A operand of
+// A packed element is P[a] * P[b] * s over the plain parameters P (SDF block
+// then colour block, device FP32), with b < 0 meaning a factor 1 and a < 0 a
+// zero; the device repack evaluates it in FP32 (BF16 copies: rounded to
+// nearest even).  Recording the sources instead of the values lets the
+// packed copies follow the parameters of a training loop on the device.
+struct Src {
+    int32_t a, b;
+    float s;
+};
+static const Src kZero = {-1, -1, 0.0f};
+
+// Pack an n_out x K matrix given by m(r, k) -> Src as the A operand of
 // v_mfma_f32_32x32x2_f32: P[((t*G + g)*64 + lane)*4 + j] = m(t*32 + lane%32, 2(4g+j) + lane/32).
 template <class M>
-static void pack_a_f32(std::vector<float> &out, int n_out, int K, M m) {
+static void pack_a_f32(std::vector<Src> &out, int n_out, int K, M m) {
     int G = round8(K) / 8, nt = (n_out + 31) / 32;
     size_t base = out.size();
-    out.resize(base + (size_t)nt * G * 64 * 4, 0.0f);
+    out.resize(base + (size_t)nt * G * 64 * 4, kZero);
     for (int t = 0; t < nt; ++t)
         for (int g = 0; g < G; ++g)
             for (int lane = 0; lane < 64; ++lane)
                 for (int j = 0; j < 4; ++j) {
                     int r = t * 32 + (lane & 31), k = 2 * (4 * g + j) + (lane >> 5);
-                    if (r < n_out && k < K)
-                        out[base + ((size_t)(t * G + g) * 64 + lane) * 4 + j] = (float)m(r, k);
+                    if (r < n_out && k < K) out[base + ((size_t)(t * G + g) * 64 + lane) * 4 + j] = m(r, k);
                 }
-}
-
-static uint16_t to_bf16(float x) {
-    uint32_t u;
-    memcpy(&u, &x, 4);
-    if ((u & 0x7f800000u) == 0x7f800000u) return (uint16_t)(u >> 16);  // inf / nan
-    u += 0x7fffu + ((u >> 16) & 1u);                                      // round to nearest even
-    return (uint16_t)(u >> 16);
 }
 
 // Pack an n_out x K matrix given by m(r, k) as the A operand of
 // v_mfma_f32_32x32x16_bf16:
 // P[((t*K16 + kk)*64 + lane)*8 + j] = bf16(m(t*32 + lane%32, 16 kk + 8 (lane/32) + j)).
 template <class M>
-static void pack_a_bf16(std::vector<uint16_t> &out, int n_out, int K, M m) {
+static void pack_a_bf16(std::vector<Src> &out, int n_out, int K, M m) {
     int K16 = (K + 15) / 16, nt = (n_out + 31) / 32;
     size_t base = out.size();
-    out.resize(base + (size_t)nt * K16 * 64 * 8, 0);
+    out.resize(base + (size_t)nt * K16 * 64 * 8, kZero);
     for (int t = 0; t < nt; ++t)
         for (int kk = 0; kk < K16; ++kk)
             for (int lane = 0; lane < 64; ++lane)
                 for (int j = 0; j < 8; ++j) {
                     int r = t * 32 + (lane & 31), k = 16 * kk + 8 * (lane >> 5) + j;
                     if (r < n_out && k < K)
-                        out[base + ((size_t)(t * K16 + kk) * 64 + lane) * 8 + j] =
-                            to_bf16((float)m(r, k));
+                        out[base + ((size_t)(t * K16 + kk) * 64 + lane) * 8 + j] = m(r, k);
                 }
 }
 
-static void pack_bias(std::vector<float> &out, const std::vector<float> &b, int n_out) {
-    int nt = (n_out + 31) / 32;
+// bias rows b(r) for r < n_out, zero padded to whole tiles
+template <class B>
+static void pack_bias(std::vector<Src> &out, B b, int n_out) {
     size_t base = out.size();
-    out.resize(base + (size_t)nt * 32, 0.0f);
-    for (int r = 0; r < n_out; ++r) out[base + r] = b[r];
-    while (out.size() % 4) out.push_back(0.0f);   // keep sub-arrays 16-byte aligned
+    int nt = (n_out + 31) / 32;
+    out.resize(base + (size_t)nt * 32, kZero);
+    for (int r = 0; r < n_out; ++r) out[base + r] = b(r);
+    while (out.size() % 4) out.push_back(kZero);   // keep sub-arrays 16-byte aligned
+}
+
+__device__ __forceinline__ float src_value(const float *P, const Src &e) {
+    if (e.a < 0) return 0.0f;
+    float v = P[e.a];
+    if (e.b >= 0) v *= P[e.b];
+    return v * e.s;
+}
+
+__global__ void k_repack(const float *__restrict__ P, const Src *__restrict__ pf, int64_t nf,
+                         float *__restrict__ df, const Src *__restrict__ pb, int64_t nb,
+                         uint16_t *__restrict__ db) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < nf) df[i] = src_value(P, pf[i]);
+    if (i < nb) {
+        const __bf16 h = (__bf16)src_value(P, pb[i]);   // round to nearest even
+        db[i] = __builtin_bit_cast(uint16_t, h);
+    }
+}
+
+int repack(const tsdfs_field *F, hipStream_t st) {
+    const int64_t n = F->n_pf > F->n_pb ? F->n_pf : F->n_pb;
+    if (n == 0) return 0;
+    hipLaunchKernelGGL(k_repack, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st,
+                       F->params_sdf, (const Src *)F->plan_f, (int64_t)F->n_pf, F->dev,
+                       (const Src *)F->plan_b, (int64_t)F->n_pb, F->devb);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
 }  // namespace tsdfs
@@ -118,113 +148,9 @@ int tsdfs_field_create(const tsdfs_field_desc *d, const float *sdf_params,
     Q.scale = P.scale;
     for (int a = 0; a < 3; ++a) Q.center[a] = P.center[a];
 
-    // Every layer of both plans from one matrix view m(r, k) (double);
-    // bscale multiplies the BF16 copy only.  Offsets into the host buffers
-    // are resolved to device pointers after the upload.
-    std::vector<float> buf;
-    std::vector<uint16_t> bbuf;
-    struct Ref { Layer *L; BLayer *B; size_t w, wb, b; bool has_b; };
-    std::vector<Ref> refs;
-    auto add = [&](Layer *L, BLayer *B, int n_out, int K, auto m, const std::vector<float> &bias,
-                   double bscale) {
-        L->K8 = round8(K);
-        B->K16 = (K + 15) / 16;
-        L->n_tiles = B->n_tiles = (n_out + 31) / 32;
-        L->n_out = B->n_out = n_out;
-        size_t w = buf.size();
-        pack_a_f32(buf, n_out, K, m);
-        size_t wb = bbuf.size();
-        pack_a_bf16(bbuf, n_out, K, [&](int r, int k) { return m(r, k) * bscale; });
-        size_t b = buf.size();
-        if (!bias.empty()) pack_bias(buf, bias, n_out);
-        refs.push_back({L, B, w, wb, b, !bias.empty()});
-    };
-    const double rs2 = 0.70710678118654752440;
+    // layer offsets into the plain parameters (SDF block, then colour block)
     const int nf = d->n_feat;
-    const float *pp = sdf_params;
-    std::vector<const float *> Ws(d->n_hidden);
-    for (int l = 0; l < d->n_hidden; ++l) {
-        Ws[l] = pp;
-        pp += (size_t)dout[l] * din[l] + dout[l];
-    }
-    const float *Wout = pp;                            // [1 + n_feat][W]
-    const float *bout = pp + (size_t)(1 + nf) * W;
-    for (int l = 0; l < d->n_hidden; ++l) {
-        const float *Wl = Ws[l], *bl = Wl + (size_t)dout[l] * din[l];
-        const double sc = (l == d->skip_at) ? rs2 : 1.0;
-        const int ld = din[l];
-        add(&P.fwd[l], &Q.fwd[l], dout[l], din[l],
-            [=](int r, int k) { return Wl[(size_t)r * ld + k] * sc; },
-            std::vector<float>(bl, bl + dout[l]), 1.0);
-        // transposes: the last one also takes diag(w_f); BF16 copies take 1/255
-        const float *wfv = (l + 1 == d->n_hidden) ? Wout : nullptr;
-        add(&P.bwd[l], &Q.bwd[l], din[l], dout[l],
-            [=](int r, int k) { return Wl[(size_t)k * ld + r] * sc * (wfv ? (double)wfv[k] : 1.0); },
-            std::vector<float>(), 1.0 / 255.0);
-    }
-    {
-        std::vector<float> ob(nf + 1);
-        for (int r = 0; r < nf; ++r) ob[r] = bout[1 + r];
-        ob[nf] = bout[0];
-        add(&P.feat, &Q.feat, nf + 1, W,
-            [=](int r, int k) { return (double)(r < nf ? Wout[(size_t)(1 + r) * W + k] : Wout[k]); },
-            ob, 1.0);
-    }
     const int cin = 9 + nf;
-    const float *cc = color_params;
-    for (int l = 0; l < d->col_hidden; ++l) {
-        const int K = l == 0 ? cin : W;
-        const float *Wl = cc;
-        std::vector<float> cb(cc + (size_t)W * K, cc + (size_t)W * K + W);
-        if (l == 0)   // input order [feat, x_hat, v, grad f]
-            add(&P.col[l], &Q.col[l], W, K,
-                [=](int r, int k) { return (double)Wl[(size_t)r * K + (k < nf ? 9 + k : k - nf)]; },
-                cb, 1.0);
-        else
-            add(&P.col[l], &Q.col[l], W, K,
-                [=](int r, int k) { return (double)Wl[(size_t)r * K + k]; }, cb, 1.0);
-        cc += (size_t)W * K + W;
-    }
-    add(&P.rgb, &Q.rgb, 3, W, [=](int r, int k) { return (double)cc[(size_t)r * W + k]; },
-        std::vector<float>(cc + (size_t)3 * W, cc + (size_t)3 * W + 3), 1.0);
-
-    // one allocation: FP32 block, then the BF16 block (256-byte aligned)
-    const size_t fbytes = (buf.size() * sizeof(float) + 255) / 256 * 256;
-    const size_t bbytes = bbuf.size() * sizeof(uint16_t);
-    hipError_t e = hipMalloc((void **)&F->dev, fbytes + bbytes);
-    uint16_t *devb = (uint16_t *)((char *)F->dev + fbytes);
-    if (e == hipSuccess)
-        e = hipMemcpy(F->dev, buf.data(), buf.size() * sizeof(float), hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = hipMemcpy(devb, bbuf.data(), bbytes, hipMemcpyHostToDevice);
-    if (e != hipSuccess) {
-        if (F->dev) (void)hipFree(F->dev);
-        delete F;
-        set_error("device allocation / copy failed: %s", hipGetErrorString(e));
-        return TSDFS_EHIP;
-    }
-    for (auto &r : refs) {
-        r.L->W = F->dev + r.w;
-        r.B->W = (const bf16x8 *)(devb + r.wb);
-        r.L->b = r.B->b = r.has_b ? F->dev + r.b : nullptr;
-    }
-    // the output layer as two views: the feature tiles, then the f tile
-    const int nft = nf / 32;
-    P.fout = P.feat;
-    P.fout.W = P.feat.W + (size_t)nft * (P.feat.K8 / 8) * 64 * 4;
-    P.fout.b = P.feat.b + (size_t)nft * 32;
-    P.fout.n_tiles = 1;
-    P.fout.n_out = 1;
-    P.feat.n_tiles = nft;
-    P.feat.n_out = nf;
-    Q.fout = Q.feat;
-    Q.fout.W = Q.feat.W + (size_t)nft * Q.feat.K16 * 64;
-    Q.fout.b = Q.feat.b + (size_t)nft * 32;
-    Q.fout.n_tiles = 1;
-    Q.fout.n_out = 1;
-    Q.feat.n_tiles = nft;
-    Q.feat.n_out = nf;
-
-    // plain parameter copies and layer offsets for the backward pass
     F->n_lin = d->n_hidden + 1;
     {
         size_t off = 0;
@@ -247,20 +173,128 @@ int tsdfs_field_create(const tsdfs_field_desc *d, const float *sdf_params,
             off += F->cdout[l];
         }
         F->n_col = off;
-        e = hipMalloc((void **)&F->params_sdf, (F->n_sdf + F->n_col) * sizeof(float));
-        if (e == hipSuccess)
-            e = hipMemcpy(F->params_sdf, sdf_params, F->n_sdf * sizeof(float), hipMemcpyHostToDevice);
-        F->params_col = F->params_sdf + F->n_sdf;
-        if (e == hipSuccess)
-            e = hipMemcpy(F->params_col, color_params, F->n_col * sizeof(float), hipMemcpyHostToDevice);
-        if (e != hipSuccess) {
-            set_error("parameter upload failed: %s", hipGetErrorString(e));
-            if (F->params_sdf) (void)hipFree(F->params_sdf);
-            (void)hipFree(F->dev);
-            delete F;
-            return TSDFS_EHIP;
-        }
     }
+
+    // Every layer of both plans as a source view m(r, k) -> Src over the
+    // plain parameters; bscale multiplies the BF16 copy only.  Offsets into
+    // the packed blocks are resolved to device pointers after allocation.
+    std::vector<Src> pf, pb;
+    struct Ref { Layer *L; BLayer *B; size_t w, wb, b; bool has_b; };
+    std::vector<Ref> refs;
+    auto add = [&](Layer *L, BLayer *B, int n_out, int K, auto m, bool has_bias, auto bias,
+                   float bscale) {
+        L->K8 = round8(K);
+        B->K16 = (K + 15) / 16;
+        L->n_tiles = B->n_tiles = (n_out + 31) / 32;
+        L->n_out = B->n_out = n_out;
+        size_t w = pf.size();
+        pack_a_f32(pf, n_out, K, m);
+        size_t wb = pb.size();
+        pack_a_bf16(pb, n_out, K, [&](int r, int k) {
+            Src e = m(r, k);
+            e.s *= bscale;
+            return e;
+        });
+        size_t b = pf.size();
+        if (has_bias) pack_bias(pf, bias, n_out);
+        refs.push_back({L, B, w, wb, b, has_bias});
+    };
+    auto src = [](int64_t a, int64_t b, float sc) { return Src{(int32_t)a, (int32_t)b, sc}; };
+    const int32_t none = -1;
+    const float rs2 = 0.70710678118654752440f;
+    const size_t wout = F->w_off[d->n_hidden], bout = F->b_off[d->n_hidden];
+    for (int l = 0; l < d->n_hidden; ++l) {
+        const size_t wl = F->w_off[l], bl = F->b_off[l];
+        const float sc = (l == d->skip_at) ? rs2 : 1.0f;
+        const int ld = din[l];
+        add(&P.fwd[l], &Q.fwd[l], dout[l], din[l],
+            [=](int r, int k) { return Src{(int32_t)(wl + (size_t)r * ld + k), none, sc}; }, true,
+            [=](int r) { return src(bl + r, none, 1.0f); }, 1.0f);
+        // transposes: the last one also takes diag(w_f); BF16 copies take 1/255
+        const bool wf = l + 1 == d->n_hidden;
+        add(&P.bwd[l], &Q.bwd[l], din[l], dout[l],
+            [=](int r, int k) {
+                return Src{(int32_t)(wl + (size_t)k * ld + r), wf ? (int32_t)(wout + k) : none, sc};
+            },
+            false, [](int) { return kZero; }, 1.0f / 255.0f);
+    }
+    // output layer: feature rows first, the f row last
+    add(&P.feat, &Q.feat, nf + 1, W,
+        [=](int r, int k) {
+            return Src{(int32_t)(r < nf ? wout + (size_t)(1 + r) * W + k : wout + k), none, 1.0f};
+        },
+        true, [=](int r) { return src(r < nf ? bout + 1 + r : bout, none, 1.0f); }, 1.0f);
+    for (int l = 0; l < d->col_hidden; ++l) {
+        const int K = l == 0 ? cin : W;
+        const size_t wl = F->n_sdf + F->cw_off[l], bl = F->n_sdf + F->cb_off[l];
+        if (l == 0)   // input order [feat, x_hat, v, grad f]
+            add(&P.col[l], &Q.col[l], W, K,
+                [=](int r, int k) {
+                    return Src{(int32_t)(wl + (size_t)r * K + (k < nf ? 9 + k : k - nf)), none, 1.0f};
+                },
+                true, [=](int r) { return src(bl + r, none, 1.0f); }, 1.0f);
+        else
+            add(&P.col[l], &Q.col[l], W, K,
+                [=](int r, int k) { return Src{(int32_t)(wl + (size_t)r * K + k), none, 1.0f}; },
+                true, [=](int r) { return src(bl + r, none, 1.0f); }, 1.0f);
+    }
+    {
+        const size_t wl = F->n_sdf + F->cw_off[d->col_hidden], bl = F->n_sdf + F->cb_off[d->col_hidden];
+        add(&P.rgb, &Q.rgb, 3, W,
+            [=](int r, int k) { return Src{(int32_t)(wl + (size_t)r * W + k), none, 1.0f}; }, true,
+            [=](int r) { return src(bl + r, none, 1.0f); }, 1.0f);
+    }
+
+    // device blocks: packed FP32, then packed BF16 (256-byte aligned); the
+    // plain parameters; the two gather plans
+    const size_t fbytes = (pf.size() * sizeof(float) + 255) / 256 * 256;
+    const size_t bbytes = pb.size() * sizeof(uint16_t);
+    hipError_t e = hipMalloc((void **)&F->dev, fbytes + bbytes);
+    if (e == hipSuccess) e = hipMalloc((void **)&F->params_sdf, (F->n_sdf + F->n_col) * sizeof(float));
+    if (e == hipSuccess) e = hipMalloc(&F->plan_f, (pf.size() + pb.size()) * sizeof(Src));
+    if (e == hipSuccess) {
+        F->devb = (uint16_t *)((char *)F->dev + fbytes);
+        F->params_col = F->params_sdf + F->n_sdf;
+        F->plan_b = (Src *)F->plan_f + pf.size();
+        F->n_pf = pf.size();
+        F->n_pb = pb.size();
+        e = hipMemcpy(F->params_sdf, sdf_params, F->n_sdf * sizeof(float), hipMemcpyHostToDevice);
+    }
+    if (e == hipSuccess)
+        e = hipMemcpy(F->params_col, color_params, F->n_col * sizeof(float), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(F->plan_f, pf.data(), pf.size() * sizeof(Src), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(F->plan_b, pb.data(), pb.size() * sizeof(Src), hipMemcpyHostToDevice);
+    if (e == hipSuccess && repack(F, nullptr) != 0) e = hipErrorLaunchFailure;
+    if (e == hipSuccess) e = hipStreamSynchronize(nullptr);
+    if (e != hipSuccess) {
+        set_error("device allocation / packing failed: %s", hipGetErrorString(e));
+        if (F->dev) (void)hipFree(F->dev);
+        if (F->params_sdf) (void)hipFree(F->params_sdf);
+        if (F->plan_f) (void)hipFree(F->plan_f);
+        delete F;
+        return TSDFS_EHIP;
+    }
+    for (auto &r : refs) {
+        r.L->W = F->dev + r.w;
+        r.B->W = (const bf16x8 *)(F->devb + r.wb);
+        r.L->b = r.B->b = r.has_b ? F->dev + r.b : nullptr;
+    }
+    // the output layer as two views: the feature tiles, then the f tile
+    const int nft = nf / 32;
+    P.fout = P.feat;
+    P.fout.W = P.feat.W + (size_t)nft * (P.feat.K8 / 8) * 64 * 4;
+    P.fout.b = P.feat.b + (size_t)nft * 32;
+    P.fout.n_tiles = 1;
+    P.fout.n_out = 1;
+    P.feat.n_tiles = nft;
+    P.feat.n_out = nf;
+    Q.fout = Q.feat;
+    Q.fout.W = Q.feat.W + (size_t)nft * Q.feat.K16 * 64;
+    Q.fout.b = Q.feat.b + (size_t)nft * 32;
+    Q.fout.n_tiles = 1;
+    Q.fout.n_out = 1;
+    Q.feat.n_tiles = nft;
+    Q.feat.n_out = nf;
     int dev = 0, n_cu = 0;
     (void)hipGetDevice(&dev);
     (void)hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev);
@@ -274,7 +308,25 @@ int tsdfs_field_destroy(tsdfs_field *F) {
     release_blas(F);
     if (F->dev) (void)hipFree(F->dev);
     if (F->params_sdf) (void)hipFree(F->params_sdf);
+    if (F->plan_f) (void)hipFree(F->plan_f);
     delete F;
+    return TSDFS_OK;
+}
+
+int tsdfs_field_params(tsdfs_field *F, float **params_dev, size_t *n_sdf, size_t *n_color) {
+    TSDFS_CHECK_ARG(F && params_dev && n_sdf && n_color, "NULL argument");
+    *params_dev = F->params_sdf;
+    *n_sdf = F->n_sdf;
+    *n_color = F->n_col;
+    return TSDFS_OK;
+}
+
+int tsdfs_field_repack(tsdfs_field *F, void *stream) {
+    TSDFS_CHECK_ARG(F, "field is NULL");
+    if (repack(F, as_stream(stream)) != 0) {
+        set_error("repack launch failed");
+        return TSDFS_EHIP;
+    }
     return TSDFS_OK;
 }
 

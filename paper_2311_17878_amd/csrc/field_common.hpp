@@ -78,6 +78,7 @@ typedef NetPlan<Layer> Plan;
 typedef NetPlan<BLayer> BPlan;
 
 void release_blas(tsdfs_field *F);
+int repack(const tsdfs_field *F, hipStream_t stream);
 
 int launch_field_bf16(const BPlan &P, int grid, const float *o, const float *v, const float *t,
                       const int32_t *ray_id, int64_t s_cap, const int64_t *s_count, float *f,
@@ -93,6 +94,10 @@ struct tsdfs_field {
     tsdfs::Plan plan;
     tsdfs::BPlan bplan;
     float *dev = nullptr;        // all packed weights (FP32 + BF16 blocks)
+    uint16_t *devb = nullptr;    // the BF16 block inside dev
+    void *plan_f = nullptr;      // gather plans of the FP32 and BF16 blocks
+    void *plan_b = nullptr;      //   (one allocation, plan_b after plan_f)
+    size_t n_pf = 0, n_pb = 0;
     int n_wg = 0;                // compute units
     // plain row-major FP32 parameters (host layout) for the backward pass
     float *params_sdf = nullptr, *params_col = nullptr;

@@ -641,4 +641,29 @@ int rgb_loss(const float *rgb, const float *target, int64_t n_rays, float *d_rgb
     return TSDFS_OK;
 }
 
+// Adam (the optimiser of the NeuS-family training the paper builds on):
+// m = b1 m + (1 - b1) g, v = b2 v + (1 - b2) g^2,
+// p -= lr (m / (1 - b1^t)) / (sqrt(v / (1 - b2^t)) + eps).
+int adam_step(float *params, const float *grad, float *m, float *v, int64_t n, float lr,
+              float beta1, float beta2, float eps, int32_t step, void *stream) {
+    TSDFS_CHECK_ARG(n >= 0 && step >= 1, "need n >= 0 and step >= 1");
+    TSDFS_CHECK_ARG(beta1 >= 0.0f && beta1 < 1.0f && beta2 >= 0.0f && beta2 < 1.0f && eps > 0.0f,
+                    "need 0 <= beta < 1 and eps > 0");
+    if (n == 0) return TSDFS_OK;
+    TSDFS_CHECK_ARG(params && grad && m && v, "NULL array argument");
+    const float c1 = (float)(1.0 - pow((double)beta1, step));
+    const float c2 = (float)(1.0 - pow((double)beta2, step));
+    map(n, as_stream(stream), [=] __device__(int64_t i) {
+        const float g = grad[i];
+        const float mi = beta1 * m[i] + (1.0f - beta1) * g;
+        const float vi = beta2 * v[i] + (1.0f - beta2) * g * g;
+        m[i] = mi;
+        v[i] = vi;
+        params[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+    });
+    TSDFS_LAUNCH_CHECK();
+    return TSDFS_OK;
+}
+
 }  // extern "C"
+

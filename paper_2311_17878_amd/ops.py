@@ -228,6 +228,14 @@ def hs_upsample(t_coarse, f_coarse, t_out, s, n_coarse=64, n_fine=64):
     return dict(t=t, dt=dt, ray_id=rid, offsets=off)
 
 
+def adam_step(params_ptr, grad, m, v, lr, beta1=0.9, beta2=0.999, eps=1e-8, step=1):
+    """One Adam update of the n = grad.numel() device floats at params_ptr
+    (m, v: device FP32 state of the same size)."""
+    n = grad.numel()
+    L.check(L.load().adam_step(ctypes.c_void_p(params_ptr), _p(grad), _p(m), _p(v), n, float(lr),
+                               float(beta1), float(beta2), float(eps), int(step), _stream()))
+
+
 class Field:
     """Device copy of the SDF + colour networks (packed for MFMA)."""
 
@@ -250,6 +258,28 @@ class Field:
         L.check(L.load().sdf_mlp_fwd_ws_bytes(self.handle, ctypes.byref(b)))
         self.ws_bytes = b.value
         self._ws = None
+
+    def params(self):
+        """(device pointer, n_sdf, n_color) of the plain FP32 parameters (SDF
+        block then colour block), updated in place by a training loop."""
+        ptr = ctypes.c_void_p(None)
+        ns, nc = ctypes.c_size_t(0), ctypes.c_size_t(0)
+        L.check(L.load().tsdfs_field_params(self.handle, ctypes.byref(ptr), ctypes.byref(ns),
+                                            ctypes.byref(nc)))
+        return ptr.value, ns.value, nc.value
+
+    def params_tensor(self):
+        """The plain parameters as a torch view of the field's own memory."""
+        ptr, ns, nc = self.params()
+
+        class _View:
+            __cuda_array_interface__ = {"shape": (ns + nc,), "typestr": "<f4", "data": (ptr, False),
+                                        "version": 3, "strides": None}
+        return torch.as_tensor(_View(), device=_dev())
+
+    def repack(self):
+        """Rebuild the packed forward operands from the plain parameters."""
+        L.check(L.load().tsdfs_field_repack(self.handle, _stream()))
 
     def workspace(self):
         if self._ws is None:

@@ -71,3 +71,17 @@ def test_eikonal_zero_for_exact_distance():
     gw = torch.autograd.grad(eik, [layers[0][0], layers[0][1]], allow_unused=True)
     assert eik.item() < 1e-14
     assert all(t is None or t.abs().max().item() < 1e-7 for t in gw)
+
+
+def test_adam_constant_gradient_closed_form():
+    """With a constant gradient the bias-corrected moments are g and g^2 at
+    every step, so each step moves p by lr g / (|g| + eps)."""
+    from oracle import train as OTR
+    g = np.array([0.5, -2.0, 1e-3, 0.0])
+    p = np.array([1.0, 1.0, 1.0, 1.0])
+    m = np.zeros(4)
+    v = np.zeros(4)
+    lr, eps = 1e-2, 1e-8
+    for t in range(1, 6):
+        p, m, v = OTR.adam(p, g, m, v, lr, 0.9, 0.999, eps, t)
+    np.testing.assert_allclose(p, 1.0 - 5 * lr * g / (np.abs(g) + eps), rtol=0, atol=1e-12)
