@@ -11,6 +11,8 @@ Paper passages followed:
     sets t_f; Sec. 4.2 fixes D_T = 5h, D_s = 1h, a 5x5x5 neighbourhood, M = 15.
   * Sec. 3.4 "Adaptive Sampling": equal intervals inside the bound, count
     proportional to the bound's length.
+  * Sec. 4.3: voxels no ray has updated can be filled by casting more rays
+    (frontier: where they border observed free space).
 Readings where the paper is silent are listed in the design notes and in
 ``tsdf_oracle.c``: unit integration weight, "unseen" stored as -D_T, voxel
 traversal on the 2^-20 m lattice, length measured in traversed voxels.
@@ -206,3 +208,44 @@ def containment(t_in, t_out, b, depth):
     q = lambda x: int(np.rint(x[hit].astype(np.float64) * LEN_Q).astype(np.int64).sum())
     return dict(rays=int(hit.sum()), failed=int((hit & ~inside).sum()),
                 original_q=q(orig), reduced_q=q(red))
+
+
+# neighbour order of the frontier rays: -x, +x, -y, +y, -z, +z
+_NB = ((-1, 0, 0), (1, 0, 0), (0, -1, 0), (0, 1, 0), (0, 0, -1), (0, 0, 1))
+
+
+def frontier(grid, cnt, flag_vol):
+    """Voxels no integration ray has updated (count 0) that border observed
+    free space (a 6-neighbour with count > 0 and flag bit0 clear, i.e.
+    V > D_s), in ascending linear order, each with a ray into it: from the
+    centre of its first such neighbour (order -x, +x, -y, +y, -z, +z) along
+    the axis towards it.  Centres are lo + (i + 1/2) h evaluated in FP32 as a
+    product then a sum (two roundings).  Returns idx [n], o [n,3], v [n,3]."""
+    nx, ny, nz = grid.n
+    cnt = np.asarray(cnt).reshape(nz, ny, nx)
+    fl = np.asarray(flag_vol).reshape(nz, ny, nx)
+    free = (cnt > 0) & ((fl & 1) == 0)
+    unseen = cnt == 0
+    choice = np.full((nz, ny, nx), -1, np.int64)
+    for k in range(5, -1, -1):                 # the first direction in order wins
+        dx, dy, dz = _NB[k]
+        nb = np.zeros_like(free)
+        zs = slice(max(0, -dz), nz - max(0, dz))
+        ys = slice(max(0, -dy), ny - max(0, dy))
+        xs = slice(max(0, -dx), nx - max(0, dx))
+        zs2 = slice(max(0, dz), nz + min(0, dz))
+        ys2 = slice(max(0, dy), ny + min(0, dy))
+        xs2 = slice(max(0, dx), nx + min(0, dx))
+        nb[zs, ys, xs] = free[zs2, ys2, xs2]
+        choice[unseen & nb] = k
+    idx = np.flatnonzero(choice.ravel() >= 0)
+    ks = choice.ravel()[idx]
+    x, y, z = idx % nx, (idx // nx) % ny, idx // (nx * ny)
+    d = np.array(_NB)[ks]                      # neighbour offset
+    Y = np.stack([x, y, z], 1) + d
+    h = np.float32(grid.h)
+    lo = np.float32(grid.lo)
+    o = (Y.astype(np.float32) + np.float32(0.5)) * h + lo
+    v = (-d).astype(np.float32)
+    return idx, o.astype(np.float32), v
+

@@ -322,3 +322,24 @@ def test_containment_counting_by_hand():
     assert c["rays"] == 6 and c["failed"] == 3          # the 2.0000002, MISS and INVALID rays
     assert c["original_q"] == 6 * 4 * (1 << 24)
     assert c["reduced_q"] == (1 + 4 + 1 + 1) * (1 << 24)
+
+
+def test_frontier_by_hand():
+    """A 4x3x2 grid: one free voxel, one surface voxel, the rest unseen.  The
+    frontier is the unseen 6-neighbours of the free voxel only, each with a
+    ray from the free voxel's centre along the axis towards it."""
+    from synth.configs import Grid
+    g = Grid((4, 3, 2), (-1.0, 0.5, 0.0), 0.25, 0.75, 0.25)
+    cnt = np.zeros((2, 3, 4), np.int64)
+    fl = np.ones((2, 3, 4), np.uint8)          # unseen voxels read V = -D_T <= D_s
+    cnt[0, 1, 1] = 3
+    fl[0, 1, 1] = 0                            # free (V > D_s)
+    cnt[0, 1, 2] = 2                           # seen surface voxel: not free, not unseen
+    idx, o, v = tsdf.frontier(g, cnt.ravel(), fl.ravel())
+    lin = lambda x, y, z: x + 4 * (y + 3 * z)
+    assert idx.tolist() == sorted([lin(0, 1, 0), lin(1, 0, 0), lin(1, 2, 0), lin(1, 1, 1)])
+    c = np.float32([-1.0 + 1.5 * 0.25, 0.5 + 1.5 * 0.25, 0.5 * 0.25])   # centre of (1, 1, 0)
+    assert (o == c).all()
+    d = {lin(0, 1, 0): (-1, 0, 0), lin(1, 0, 0): (0, -1, 0), lin(1, 2, 0): (0, 1, 0), lin(1, 1, 1): (0, 0, 1)}
+    for i, vv in zip(idx, v):
+        assert tuple(vv) == d[i]
