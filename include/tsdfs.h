@@ -198,6 +198,22 @@ int place_fine_samples(const int32_t *offsets_c, const float *t_c, const float *
                        int64_t s_cap, int64_t *s_total_dev, void *ws, size_t ws_bytes,
                        void *stream);
 
+/* Filling unseen voxels (Sec. 4.3: voxels no ray has updated can be filled by
+ * casting more rays).  The frontier: voxels with count 0 in `state` (an
+ * integration state) that have a 6-neighbour with count > 0 whose flags bit0
+ * (tsdf_finalize) is clear, i.e. observed free space (V > D_s).  For the
+ * i-th frontier voxel in ascending linear order (x fastest): idx[i], and
+ * the ray o[i], v[i] ([.., 3] float) from the centre of its first such
+ * neighbour (order -x, +x, -y, +y, -z, +z) along that axis towards it;
+ * centres are lo + (j + 1/2) h as an FP32 product then sum.  Integrating
+ * these rays with depths of the scene fills the voxels behind the frontier.
+ * *n_dev (int64, device) = the frontier size; entries past cap are dropped.
+ * ws: tsdf_frontier_ws_bytes.  Asynchronous on `stream`; no allocation. */
+int tsdf_frontier_ws_bytes(const tsdfs_grid *grid, size_t *bytes);
+int tsdf_frontier(const tsdfs_grid *grid, const void *state, const uint8_t *flags, int64_t cap,
+                  int32_t *idx, float *o, float *v, int64_t *n_dev, void *ws, size_t ws_bytes,
+                  void *stream);
+
 /* Recovery (Sec. 3.3, last paragraph; Sec. 4.6; supplementary Sec. B.3): a
  * ray whose weights in its bound sum to less than tau is rendered again over
  * its initial range with the conventional sampler.

@@ -54,6 +54,8 @@ SIGNATURES = {
     "tsdfs_field_params": [P, P, P, P],
     "tsdfs_field_repack": [P, P],
     "adam_step": [P, P, P, P, c_int64, c_float, c_float, c_float, c_float, c_int32, P],
+    "tsdf_frontier_ws_bytes": [P, P],
+    "tsdf_frontier": [P, P, P, c_int64, P, P, P, P, P, c_size_t, P],
     "select_rays_ws_bytes": [c_int64, P],
     "select_rays": [P, c_int64, c_float, P, P, P, c_size_t, P],
     "gather_rays": [P, P, c_int64, P, P, P, P, P],

@@ -1,9 +1,12 @@
+// Stream compactions around the render path.
 // Recovery of rays whose bound missed the surface (Sec. 3.3, last
 // paragraph; Sec. 4.6; supplementary Sec. B.3): select the rays whose weight
-// sum is below tau (a stream compaction: per-block flag counts, one scan of
-// the block totals, per-block placement in ray order), gather their origin
-// and direction for the re-render over the whole range, and scatter the
-// re-rendered outputs back.
+// sum is below tau (per-block flag counts, one scan of the block totals,
+// per-block placement in ray order), gather their origin and direction for
+// the re-render over the whole range, and scatter the re-rendered outputs
+// back.  Filling unseen voxels (Sec. 4.3): the same compaction over the
+// voxels that no ray has updated and that border observed free space, each
+// emitted with the ray that fills it.
 #include "common.hpp"
 
 namespace tsdfs {
@@ -130,6 +133,73 @@ __global__ void k_scatter_rays(const int32_t *__restrict__ idx, const int64_t *_
     acc[r] = acc_s[i];
 }
 
+// --------------------------------------------------- frontier of unseen ----
+
+struct FrontGrid {
+    int n[3];
+    float lo[3];
+    float h;
+};
+
+// First free 6-neighbour (order -x, +x, -y, +y, -z, +z) of an unseen voxel:
+// count > 0 and flag bit0 clear (V > D_s); -1 if X is seen or has none.
+__device__ __forceinline__ int front_dir(const FrontGrid &g, const uint32_t *__restrict__ cnt,
+                                         const uint8_t *__restrict__ fl, int64_t X, int c[3]) {
+    if (cnt[X] != 0) return -1;
+    const int64_t nx = g.n[0], nxy = (int64_t)g.n[0] * g.n[1];
+    c[0] = (int)(X % nx);
+    c[1] = (int)((X / nx) % g.n[1]);
+    c[2] = (int)(X / nxy);
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+        const int a = k >> 1, s = (k & 1) ? 1 : -1;
+        const int y = c[a] + s;
+        if (y < 0 || y >= g.n[a]) continue;
+        const int64_t Y = X + s * (a == 0 ? 1 : a == 1 ? nx : nxy);
+        if (cnt[Y] > 0 && (fl[Y] & 1u) == 0) return k;
+    }
+    return -1;
+}
+
+__global__ void __launch_bounds__(kSelBlock) k_front_count(FrontGrid g, const uint32_t *__restrict__ cnt,
+                                                           const uint8_t *__restrict__ fl, int64_t N,
+                                                           int64_t *__restrict__ block_sum) {
+    __shared__ int lds4[4];
+    const int64_t X = blockIdx.x * (int64_t)kSelBlock + threadIdx.x;
+    int c[3];
+    const int x = X < N && front_dir(g, cnt, fl, X, c) >= 0 ? 1 : 0;
+    int tot;
+    sel_block_scan(x, lds4, &tot);
+    if (threadIdx.x == 0) block_sum[blockIdx.x] = tot;
+}
+
+// Frontier voxel i (ascending): idx, and the ray from its free neighbour's
+// centre along the axis towards it; centres lo + (j + 1/2) h as an FP32
+// product then sum.  Entries past cap are dropped.
+__global__ void __launch_bounds__(kSelBlock) k_front_place(FrontGrid g, const uint32_t *__restrict__ cnt,
+                                                           const uint8_t *__restrict__ fl, int64_t N,
+                                                           const int64_t *__restrict__ block_off,
+                                                           int64_t cap, int32_t *__restrict__ idx,
+                                                           float *__restrict__ o, float *__restrict__ v) {
+    __shared__ int lds4[4];
+    const int64_t X = blockIdx.x * (int64_t)kSelBlock + threadIdx.x;
+    int c[3];
+    const int k = X < N ? front_dir(g, cnt, fl, X, c) : -1;
+    int tot;
+    const int ex = sel_block_scan(k >= 0 ? 1 : 0, lds4, &tot);
+    if (k < 0) return;
+    const int64_t i = block_off[blockIdx.x] + ex;
+    if (i >= cap) return;
+    idx[i] = (int32_t)X;
+    const int a = k >> 1, s = (k & 1) ? 1 : -1;
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+        const int y = c[b] + (b == a ? s : 0);
+        o[3 * i + b] = __fadd_rn(__fmul_rn((float)y + 0.5f, g.h), g.lo[b]);
+        v[3 * i + b] = b == a ? (float)(-s) : 0.0f;
+    }
+}
+
 static unsigned nblocks(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
 
 }  // namespace tsdfs
@@ -193,4 +263,47 @@ int scatter_rays(const int32_t *idx, const int64_t *n_sel_dev, int64_t cap, cons
     return TSDFS_OK;
 }
 
+int tsdf_frontier_ws_bytes(const tsdfs_grid *grid, size_t *bytes) {
+    LatGrid g;
+    int rc = make_lat_grid(grid, &g);
+    if (rc) return rc;
+    TSDFS_CHECK_ARG(bytes, "NULL argument");
+    const int64_t N = (int64_t)g.n[0] * g.n[1] * g.n[2];
+    const int64_t nb = (N + kSelBlock - 1) / kSelBlock;
+    *bytes = (size_t)(2 * nb + 1) * sizeof(int64_t);
+    return TSDFS_OK;
+}
+
+int tsdf_frontier(const tsdfs_grid *grid, const void *state, const uint8_t *flags, int64_t cap,
+                  int32_t *idx, float *o, float *v, int64_t *n_dev, void *ws, size_t ws_bytes,
+                  void *stream) {
+    LatGrid lg;
+    int rc = make_lat_grid(grid, &lg);
+    if (rc) return rc;
+    TSDFS_CHECK_ARG(state && flags && n_dev, "NULL argument");
+    TSDFS_CHECK_ARG(cap >= 0, "cap must be >= 0");
+    TSDFS_CHECK_ARG(cap == 0 || (idx && o && v), "NULL output array");
+    size_t need;
+    tsdf_frontier_ws_bytes(grid, &need);
+    TSDFS_CHECK_ARG(ws && ws_bytes >= need, "workspace too small (%zu < %zu)", ws_bytes, need);
+    FrontGrid g;
+    for (int a = 0; a < 3; ++a) {
+        g.n[a] = grid->n[a];
+        g.lo[a] = grid->lo[a];
+    }
+    g.h = grid->h;
+    const int64_t N = (int64_t)g.n[0] * g.n[1] * g.n[2];
+    const uint32_t *cnt = (const uint32_t *)((const int64_t *)state + N);
+    hipStream_t st = as_stream(stream);
+    const int64_t nb = (N + kSelBlock - 1) / kSelBlock;
+    int64_t *block_sum = (int64_t *)ws, *block_off = block_sum + nb;
+    hipLaunchKernelGGL(k_front_count, dim3(nb), dim3(kSelBlock), 0, st, g, cnt, flags, N, block_sum);
+    hipLaunchKernelGGL(k_sel_scan, dim3(1), dim3(1024), 0, st, block_sum, nb, block_off, n_dev);
+    hipLaunchKernelGGL(k_front_place, dim3(nb), dim3(kSelBlock), 0, st, g, cnt, flags, N, block_off,
+                       cap, idx, o, v);
+    TSDFS_LAUNCH_CHECK();
+    return TSDFS_OK;
+}
+
 }  // extern "C"
+

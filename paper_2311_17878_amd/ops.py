@@ -175,6 +175,22 @@ def bound_stats(t_in, t_out, bounds, depth):
     return out
 
 
+def frontier(grid, state, flags, cap):
+    """Unseen voxels bordering observed free space and the rays that fill
+    them: dict idx, o, v (room for cap) and the device count n."""
+    d = _dev()
+    idx = torch.empty(max(cap, 1), dtype=torch.int32, device=d)
+    o = torch.empty((max(cap, 1), 3), dtype=torch.float32, device=d)
+    v = torch.empty((max(cap, 1), 3), dtype=torch.float32, device=d)
+    n = torch.zeros(1, dtype=torch.int64, device=d)
+    b = ctypes.c_size_t(0)
+    L.check(L.load().tsdf_frontier_ws_bytes(ctypes.byref(grid), ctypes.byref(b)))
+    ws = torch.empty(max(b.value, 8), dtype=torch.uint8, device=d)
+    L.check(L.load().tsdf_frontier(ctypes.byref(grid), _p(state), _p(flags), cap, _p(idx), _p(o),
+                                   _p(v), _p(n), _p(ws), ws.numel(), _stream()))
+    return dict(idx=idx, o=o, v=v, n=n)
+
+
 def select_rays(acc, tau):
     """Rays to recover (weight sum not >= tau), ascending; returns the index
     array (room for every ray) and the device count."""

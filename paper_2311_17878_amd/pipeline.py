@@ -60,6 +60,32 @@ class TsdfRenderer:
         self.V, self.flags = ops.finalize(self.grid, self.state, want_v)
         return self.V, self.flags
 
+    def fill_unseen(self, depth_of, max_iter=4, cap=1 << 20):
+        """Cast more rays into the voxels no ray has updated (Sec. 4.3): each
+        round finds the frontier (unseen voxels next to observed free space)
+        and its rays on the device, takes their depths from depth_of(o, v)
+        (host arrays; the scene's depth source) and integrates them, until the
+        frontier is empty or max_iter rounds ran.  A ray origin is a voxel
+        centre that fusion calls free, which near silhouettes can lie just
+        inside a solid: depth_of must then report a short valid depth (a
+        blocked sensor), since a missing reading integrates as free space and
+        would open the solid's interior.  Returns the frontier sizes and
+        leaves the volume finalized."""
+        sizes = []
+        for _ in range(max_iter):
+            self.finalize(want_v=False)
+            fr = ops.frontier(self.grid, self.state, self.flags, cap)
+            n = int(fr["n"].item())
+            sizes.append(n)
+            if n == 0:
+                break
+            k = min(n, cap)
+            o, v = fr["o"][:k], fr["v"][:k]
+            d = torch.as_tensor(depth_of(o.cpu().numpy(), v.cpu().numpy()), dtype=torch.float32)
+            self.integrate(o, v, d.to(o.device), batch=k)
+        self.finalize()
+        return sizes
+
     # ---------------------------------------------------------- render ----
     def render(self, o, v, sync=False, keep=False, events=None):
         """Render rays o, v [R,3].  `events`: optional dict that receives

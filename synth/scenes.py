@@ -204,6 +204,16 @@ def ray_depth(scene, o32, v32):
     return d.astype(np.float32)
 
 
+def sensor_depth(scene, o32, v32):
+    """Depth reading of rays whose origins may lie anywhere, e.g. rays cast
+    from voxel centres to fill unseen space: a sensor whose origin is inside
+    a solid (clearance < 0) is blocked at once and reports the shortest valid
+    depth, 2^-16 m (a zero or missing reading would mean free space)."""
+    d = ray_depth(scene, o32, v32)
+    inside = scene.clearance(o32.astype(np.float64)) < 0
+    return np.where(inside, np.float32(2.0 ** -16), d).astype(np.float32)
+
+
 def surface_normal(prim, p):
     """Outward (towards free space) unit normal of `prim` at surface points p."""
     p = np.atleast_2d(np.asarray(p, np.float64))

@@ -343,3 +343,34 @@ def test_frontier_by_hand():
     d = {lin(0, 1, 0): (-1, 0, 0), lin(1, 0, 0): (0, -1, 0), lin(1, 2, 0): (0, 1, 0), lin(1, 1, 1): (0, 0, 1)}
     for i, vv in zip(idx, v):
         assert tuple(vv) == d[i]
+
+
+def test_frontier_fill_covers_free_space_small_scene():
+    """Filling the small scene's unseen voxels (Sec. 4.3) from the oracle's
+    frontier, with depths read by a sensor at each ray's origin: the rounds
+    end with an empty frontier, every voxel whose centre is in free space
+    has been updated, and no updated voxel lies deeper inside an object than
+    the truncation D_T plus a voxel diagonal (integration stops at s <= -D_T)."""
+    from synth.scenes import sensor_depth
+    cfg = get_config("c1")
+    g, sc = cfg.grid, cfg.scene()
+    o, v, d = cfg.integration_rays()
+    st = tsdf.integrate(g, o, v, d, tie_eps=1e-9)
+    nx, ny, nz = g.n
+    i = np.arange(g.n_vox)
+    c = np.stack([i % nx, (i // nx) % ny, i // (nx * ny)], 1) * g.h + np.array(g.lo) + 0.5 * g.h
+    cl = sc.clearance(c)
+    assert ((st.cnt == 0) & (cl > g.h)).any()      # the views leave free space unseen
+    sizes = []
+    for _ in range(4):
+        fl = tsdf.flags(g, tsdf.finalize(g, st))
+        idx, fo, fv = tsdf.frontier(g, st.cnt, fl)
+        sizes.append(idx.size)
+        if idx.size == 0:
+            break
+        st.add(fo, fv, sensor_depth(sc, fo, fv), 1e-9)
+    assert sizes[0] > 0 and sizes[-1] == 0
+    seen = st.cnt > 0
+    assert not (~seen & (cl > 0)).any()
+    assert not (seen & (cl < -(g.d_t + np.sqrt(3.0) * g.h))).any()
+    assert (~seen & (cl < -(g.d_t + np.sqrt(3.0) * g.h))).sum() > 1000   # interiors stay unseen
