@@ -130,6 +130,8 @@ def main():
                     help="weight-sum threshold of the recovery leg (0: skip the leg)")
     ap.add_argument("--full-fine", type=int, default=8,
                     help="fine samples per ray of the coarse + fine leg (0: skip the leg)")
+    ap.add_argument("--fill-rounds", type=int, default=2,
+                    help="rounds of filling unseen voxels on a copy of the volume (0: skip)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a device-to-device copy of MIB MiB (to scale HBM counters)")
     args = ap.parse_args()
@@ -467,6 +469,68 @@ def main():
                 "optimizer": "Adam lr 5e-4 (device), packed operands rebuilt every step",
             }
             log(f"{lname}: {lms:.2f} ms/step, loss {hist[0][0]:.5f} -> {hist[-1][0]:.5f}")
+
+    # ---- filling unseen voxels (Sec. 4.3) on a copy of the fused volume:
+    # per round the flags, the frontier and its rays on the device, depths
+    # from a sensor at each ray's origin (host, not timed), and the fill
+    # rays fused; then the render step on the filled volume
+    if args.fill_rounds > 0:
+        from synth.scenes import sensor_depth
+        scene = cfg.scene()
+        Rf = TsdfRenderer(grid, field, s.rho_num, s.rho_den, s.n_min, s.n_max, cfg.neus_s,
+                          s.t_far, prec)
+        Rf.state = R.state.clone()
+        N = g.n_vox
+        seen = lambda st: int((st[8 * N: 12 * N].view(torch.int32) != 0).sum().item())
+        rounds = []
+        seen0 = seen(Rf.state)
+        cap = 1 << 22
+        for _ in range(args.fill_rounds):
+            torch.cuda.synchronize()
+            e0.record()
+            Rf.finalize(want_v=False)
+            e1.record()
+            e2, e3 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e2.record()
+            fr = ops.frontier(grid, Rf.state, Rf.flags, cap)
+            e3.record()
+            n = int(fr["n"].item())
+            r_ = {"frontier": n, "finalize_ms": e0.elapsed_time(e1),
+                  "frontier_ms": e2.elapsed_time(e3)}
+            if n == 0:
+                rounds.append(r_)
+                break
+            k = min(n, cap)
+            h0 = time.time()
+            dfill = sensor_depth(scene, fr["o"][:k].cpu().numpy(), fr["v"][:k].cpu().numpy())
+            r_["host_depth_s"] = time.time() - h0
+            dfill = dev(dfill)
+            nup_f = torch.zeros(1, dtype=torch.int64, device="cuda")
+            torch.cuda.synchronize()
+            e0.record()
+            Rf.integrate(fr["o"][:k], fr["v"][:k], dfill, batch=k, n_updates=nup_f)
+            e1.record()
+            torch.cuda.synchronize()
+            r_.update(integrate_ms=e0.elapsed_time(e1), voxel_updates=int(nup_f.item()),
+                      seen_after=seen(Rf.state))
+            rounds.append(r_)
+        Rf.finalize()
+        for _ in range(args.warmup):
+            Rf.render(ro_d, rv_d)
+        torch.cuda.synchronize()
+        start.record()
+        for _ in range(args.steps):
+            out_fl = Rf.render(ro_d, rv_d)
+        end.record()
+        torch.cuda.synchronize()
+        ms_fl = start.elapsed_time(end) / args.steps
+        result["fill_unseen"] = {
+            "voxels": N, "seen_before": seen0, "rounds": rounds,
+            "render_ms_per_step": ms_fl, "render_rays_per_s": n_rays / (ms_fl * 1e-3),
+            "samples_per_ray": int(out_fl["s_total"].item()) / n_rays,
+        }
+        log(f"fill unseen: {rounds}; render after {ms_fl:.3f} ms/step")
+        del Rf, fr
 
     if not args.no_hs:
         for _ in range(1):
