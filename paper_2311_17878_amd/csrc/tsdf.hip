@@ -84,49 +84,81 @@ __global__ void __launch_bounds__(256) k_integrate(LatGrid g, int64_t *__restric
                                                    const float *__restrict__ v,
                                                    const float *__restrict__ depth, int64_t n_rays,
                                                    unsigned long long *n_updates) {
-    int64_t ray = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    const int64_t ray = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    const int lane = threadIdx.x & 63;
     int64_t updates = 0;
+    bool alive = false, surface = false;
+    LatRay r;
+    Walk w;
+    int64_t A = 0, DK = 0, dA[3] = {0, 0, 0};
     if (ray < n_rays) {
         float oo[3] = {o[3 * ray], o[3 * ray + 1], o[3 * ray + 2]};
         float vv[3] = {v[3 * ray], v[3 * ray + 1], v[3 * ray + 2]};
         float D = depth[ray];
-        LatRay r;
         int32_t inn, ind, outn, outd;
-        Walk w;
         if (snap_ray(g, oo, vv, r) && grid_range(g, r, inn, ind, outn, outd) &&
             walk_begin(g, r, inn, ind, w)) {
-            bool surface = isfinite(D) && D >= 1.52587890625e-05f && D < 4096.0f;
+            alive = true;
+            surface = isfinite(D) && D >= 1.52587890625e-05f && D < 4096.0f;
             int64_t K = (int64_t)r.V[0] * r.V[0] + (int64_t)r.V[1] * r.V[1] +
                         (int64_t)r.V[2] * r.V[2];
-            // s * 2^40 = A + D K with A = V.(O - C): C is the voxel centre
-            int64_t A = 0, dA[3];
             for (int a = 0; a < 3; ++a) {
                 int64_t C = g.LO[a] + (int64_t)w.i[a] * g.H + g.H / 2;
                 A += (int64_t)r.V[a] * (r.O[a] - C);
                 dA[a] = (int64_t)(r.V[a] < 0 ? -r.V[a] : r.V[a]) * g.H;
             }
-            int64_t DK = surface ? depth_times_k(D, K - ((int64_t)1 << 40)) : 0;
-            const int64_t DT40 = g.DT40;
-            while (true) {
-                int64_t s40 = surface ? A + DK : DT40;
-                if (s40 <= -DT40) break;
+            DK = surface ? depth_times_k(D, K - ((int64_t)1 << 40)) : 0;
+        }
+    }
+    const int64_t DT40 = g.DT40;
+    // every lane of the wave takes each step together (the shuffles below
+    // need the whole wave); a lane that has finished contributes nothing
+    while (__any(alive)) {
+        int64_t s32 = 0, X = -1 - lane;          // finished lanes: a voxel of their own
+        if (alive) {
+            int64_t s40 = surface ? A + DK : DT40;
+            if (s40 <= -DT40) {
+                alive = false;
+            } else {
                 if (s40 > DT40) s40 = DT40;
-                int64_t s32 = (s40 + 128) >> 8;   // units of 2^-32 m
-                int64_t X = vox_linear(g, w.i);
-                atomicAdd((unsigned long long *)&sum[X], (unsigned long long)s32);
-                atomicAdd(&cnt[X], 1u);
-                ++updates;
-                int a = walk_exit_axis(w);
-                A -= dA[a];
-                if (!walk_step(g, w, a)) break;
+                s32 = (s40 + 128) >> 8;           // units of 2^-32 m
+                X = vox_linear(g, w.i);
             }
+        }
+        // runs of consecutive lanes on one voxel: the last lane of a run adds
+        // the run's sum and length (integer sums: the same totals in any order)
+        const int64_t Xp = __shfl_up(X, 1);
+        const int64_t Xn = __shfl_down(X, 1);
+        int head = (lane == 0 || Xp != X) ? lane : 0;
+        int64_t P = s32;
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            const int64_t tp = __shfl_up(P, d);
+            const int th = __shfl_up(head, d);
+            if (lane >= d) {
+                P += tp;
+                head = th > head ? th : head;
+            }
+        }
+        const int64_t before = __shfl(P, head > 0 ? head - 1 : 0);
+        const bool tail = lane == 63 || Xn != X;
+        if (alive && tail) {
+            atomicAdd((unsigned long long *)&sum[X],
+                      (unsigned long long)(P - (head > 0 ? before : 0)));
+            atomicAdd(&cnt[X], (uint32_t)(lane - head + 1));
+        }
+        if (alive) {
+            ++updates;
+            int a = walk_exit_axis(w);
+            A -= dA[a];
+            if (!walk_step(g, w, a)) alive = false;
         }
     }
     if (n_updates) {
         // one atomic per wave
         unsigned long long tot = (unsigned long long)updates;
         for (int off = 32; off > 0; off >>= 1) tot += __shfl_xor(tot, off);
-        if ((threadIdx.x & 63) == 0 && tot) atomicAdd(n_updates, tot);
+        if (lane == 0 && tot) atomicAdd(n_updates, tot);
     }
 }
 
