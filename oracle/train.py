@@ -2,7 +2,7 @@
 
 TEST INFRASTRUCTURE ONLY (see the package docstring).
 
-The paper only envisions moving the TSDF bounds into training (Sec. 6,
+The paper only envisions moving the TSDF bounds into training (Sec. 5,
 "Limitations and Future Work"); the step here is the workload's definition:
 
   L = (1/B) sum_rays |C_hat - C*|^2  +  lambda (1/P) sum_points (|grad f| - 1)^2

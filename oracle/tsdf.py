@@ -249,3 +249,33 @@ def frontier(grid, cnt, flag_vol):
     v = (-d).astype(np.float32)
     return idx, o.astype(np.float32), v
 
+
+
+def bricks(grid, state, B=8):
+    """Two-level layout of an integration state (the multi-resolution
+    direction of Sec. 5, limitations and future work): bricks of B^3 voxels,
+    ceil(n/B) per axis, x fastest.  A band brick holds a seen voxel whose mean
+    V is below D_T, i.e. one that received an update inside the truncation
+    band (no update exceeds D_T).  Returns band [nbz, nby, nbx] (bool) and
+    seen [N] (bool, count > 0)."""
+    d_t = float(np.float32(grid.d_t))
+    V = finalize(grid, state).ravel()
+    seen = state.cnt > 0
+    nx, ny, nz = grid.n
+    nb = [(x + B - 1) // B for x in grid.n]
+    i = np.flatnonzero(seen & (V < d_t))
+    band = np.zeros((nb[2], nb[1], nb[0]), bool)
+    band[(i // (nx * ny)) // B, ((i // nx) % ny) // B, (i % nx) // B] = True
+    return band, seen
+
+
+def bricks_expand(grid, state, band, B=8):
+    """V of the two-level volume, [nz, ny, nx]: the voxel's own mean in a band
+    brick; elsewhere D_T where seen and -D_T where unseen."""
+    d_t = float(np.float32(grid.d_t))
+    V = finalize(grid, state)
+    nx, ny, nz = grid.n
+    z, y, x = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    in_band = band[z // B, y // B, x // B]
+    seen = (state.cnt > 0).reshape(nz, ny, nx)
+    return np.where(in_band, V, np.where(seen, d_t, -d_t))
