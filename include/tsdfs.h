@@ -102,6 +102,50 @@ int tsdf_finalize(const tsdfs_grid *grid, const void *state, float *V, uint8_t *
                   void *stream);
 
 /* ---------------------------------------------------------------------------
+ * Two-level volume (the multi-resolution direction of Sec. 5, limitations
+ * and future work: raising the volume's resolution without its memory
+ * growing with it).  The grid is cut
+ * into bricks of 8^3 voxels (ceil(n/8) per axis).  The brick level keeps, per
+ * brick, one seen bit per voxel, a band flag (some update with s < D_T, i.e.
+ * inside the truncation band) and a pool slot; the voxel level keeps the
+ * integration sums and counts (same units as tsdf_integrate's state) only in
+ * the pool, for band bricks.  A brick outside the band received only updates
+ * clamped to D_T, so there a seen voxel has V = D_T and an unseen one -D_T:
+ * finalized, the two-level volume gives the flags of the dense volume and
+ * its V (exactly D_T where the dense V is D_T up to FP32 rounding of a sum).
+ *
+ * Meta (tsdf_sparse_meta_bytes, 72 bytes per brick, caller-owned device
+ * memory): seen words [n_bricks][8] u64 (word z & 7, bit 8 (y & 7) + (x & 7)),
+ * band flags [n_bricks] u32, slots [n_bricks] int32; bricks x fastest.
+ * Pool (tsdf_sparse_pool_bytes(cap) = 6144 bytes per brick): sums
+ * [cap][512] int64 then counts [cap][512] u32, voxel (x&7) + 8 (y&7) +
+ * 64 (z&7) of a brick.
+ * Sequence: tsdf_sparse_reset; tsdf_sparse_mark over every batch of rays;
+ * tsdf_sparse_alloc (band bricks get slots 0 .. n_band-1 in ascending brick
+ * order; *n_band_dev, int64 on the device; ws: tsdf_sparse_alloc_ws_bytes);
+ * a pool of cap >= n_band bricks, tsdf_sparse_pool_reset; then
+ * tsdf_sparse_accumulate over the same rays (optional n_updates_dev as in
+ * tsdf_integrate); tsdf_sparse_finalize writes V (may be NULL) and flags
+ * [N] as tsdf_finalize does.  Rays not marked before the allocation must not
+ * be accumulated (their band bricks may have no slot).  Bricks whose slot is
+ * >= cap are treated as having none, so cap below n_band loses their band
+ * values.  All asynchronous on `stream`; no allocation. */
+int tsdf_sparse_meta_bytes(const tsdfs_grid *grid, size_t *bytes);
+int tsdf_sparse_reset(const tsdfs_grid *grid, void *meta, void *stream);
+int tsdf_sparse_mark(const tsdfs_grid *grid, void *meta, const float *o, const float *v,
+                     const float *depth, int64_t n_rays, void *stream);
+int tsdf_sparse_alloc_ws_bytes(const tsdfs_grid *grid, size_t *bytes);
+int tsdf_sparse_alloc(const tsdfs_grid *grid, void *meta, int64_t *n_band_dev, void *ws,
+                      size_t ws_bytes, void *stream);
+int tsdf_sparse_pool_bytes(int64_t cap, size_t *bytes);
+int tsdf_sparse_pool_reset(int64_t cap, void *pool, void *stream);
+int tsdf_sparse_accumulate(const tsdfs_grid *grid, const void *meta, void *pool, int64_t cap,
+                           const float *o, const float *v, const float *depth, int64_t n_rays,
+                           int64_t *n_updates_dev, void *stream);
+int tsdf_sparse_finalize(const tsdfs_grid *grid, const void *meta, const void *pool, int64_t cap,
+                         float *V, uint8_t *flags, void *stream);
+
+/* ---------------------------------------------------------------------------
  * Sample-boundary detection, Alg. 1 (Sec. 3.3).  Per ray: phase 1 walks
  * voxels from max(0, grid entry) to the first with flag bit0; t_n = the
  * parameter where it is entered.  Phase 2 starts at that voxel, counts
@@ -309,7 +353,7 @@ int composite(const int32_t *offsets, int64_t n_rays, const float *v, const floa
 
 /* ---------------------------------------------------------------------------
  * Training backward (the paper envisions moving the TSDF bounds into training,
- * Sec. 6 "Limitations and Future Work"; this is one step of it).
+ * Sec. 5 "Limitations and Future Work"; this is one step of it).
  *
  * composite_bwd: adjoint of composite() for the rgb output: given d_out_rgb
  * [n_rays,3], writes per-sample d_f [S], d_grad_f [S,3] (through the NeuS

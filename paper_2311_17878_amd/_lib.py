@@ -56,6 +56,15 @@ SIGNATURES = {
     "adam_step": [P, P, P, P, c_int64, c_float, c_float, c_float, c_float, c_int32, P],
     "tsdf_frontier_ws_bytes": [P, P],
     "tsdf_frontier": [P, P, P, c_int64, P, P, P, P, P, c_size_t, P],
+    "tsdf_sparse_meta_bytes": [P, P],
+    "tsdf_sparse_reset": [P, P, P],
+    "tsdf_sparse_mark": [P, P, P, P, P, c_int64, P],
+    "tsdf_sparse_alloc_ws_bytes": [P, P],
+    "tsdf_sparse_alloc": [P, P, P, P, c_size_t, P],
+    "tsdf_sparse_pool_bytes": [c_int64, P],
+    "tsdf_sparse_pool_reset": [c_int64, P, P],
+    "tsdf_sparse_accumulate": [P, P, P, c_int64, P, P, P, c_int64, P, P],
+    "tsdf_sparse_finalize": [P, P, P, c_int64, P, P, P],
     "select_rays_ws_bytes": [c_int64, P],
     "select_rays": [P, c_int64, c_float, P, P, P, c_size_t, P],
     "gather_rays": [P, P, c_int64, P, P, P, P, P],

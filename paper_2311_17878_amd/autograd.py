@@ -1,5 +1,5 @@
 """torch.autograd.Function wrappers around the hand-written backward, and one
-TSDF-bounded training step (the paper's future-work direction of Sec. 6,
+TSDF-bounded training step (the paper's future-work direction of Sec. 5,
 moving the TSDF bounds into training).
 
 All arithmetic runs in libtsdfs.so: forward through sdf_mlp_fwd / composite,

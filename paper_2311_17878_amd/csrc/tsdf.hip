@@ -78,6 +78,113 @@ __device__ __forceinline__ int64_t depth_times_k(float D, int64_t dK) {
     return hi + q;
 }
 
+// One ray's integration walk: the lattice ray, the walk state and the
+// projective distance s 2^40 = A + D K (A = V.(O - C) at the current voxel
+// centre C, lowered by dA[a] at each step along axis a).
+struct IntRay {
+    bool alive, surface;
+    LatRay r;
+    Walk w;
+    int64_t A, DK, dA[3];
+};
+
+__device__ __forceinline__ void int_begin(const LatGrid &g, const float *__restrict__ o,
+                                          const float *__restrict__ v,
+                                          const float *__restrict__ depth, int64_t n_rays,
+                                          int64_t ray, IntRay &q) {
+    q.alive = false;
+    q.surface = false;
+    q.A = 0;
+    q.DK = 0;
+    q.dA[0] = q.dA[1] = q.dA[2] = 0;
+    if (ray >= n_rays) return;
+    float oo[3] = {o[3 * ray], o[3 * ray + 1], o[3 * ray + 2]};
+    float vv[3] = {v[3 * ray], v[3 * ray + 1], v[3 * ray + 2]};
+    float D = depth[ray];
+    int32_t inn, ind, outn, outd;
+    if (snap_ray(g, oo, vv, q.r) && grid_range(g, q.r, inn, ind, outn, outd) &&
+        walk_begin(g, q.r, inn, ind, q.w)) {
+        q.alive = true;
+        q.surface = isfinite(D) && D >= 1.52587890625e-05f && D < 4096.0f;
+        int64_t K = (int64_t)q.r.V[0] * q.r.V[0] + (int64_t)q.r.V[1] * q.r.V[1] +
+                    (int64_t)q.r.V[2] * q.r.V[2];
+        for (int a = 0; a < 3; ++a) {
+            int64_t C = g.LO[a] + (int64_t)q.w.i[a] * g.H + g.H / 2;
+            q.A += (int64_t)q.r.V[a] * (q.r.O[a] - C);
+            q.dA[a] = (int64_t)(q.r.V[a] < 0 ? -q.r.V[a] : q.r.V[a]) * g.H;
+        }
+        q.DK = q.surface ? depth_times_k(D, K - ((int64_t)1 << 40)) : 0;
+    }
+}
+
+// The update a live ray makes at its current voxel: s in units of 2^-32 m
+// (clamped to D_T), the voxel's linear index, and whether s was below D_T
+// (inside the truncation band).  A ray whose s reaches -D_T stops here.
+__device__ __forceinline__ bool int_update(const LatGrid &g, IntRay &q, int64_t &X, int64_t &s32,
+                                           bool &band) {
+    if (!q.alive) return false;
+    int64_t s40 = q.surface ? q.A + q.DK : g.DT40;
+    if (s40 <= -g.DT40) {
+        q.alive = false;
+        return false;
+    }
+    band = s40 < g.DT40;
+    if (!band) s40 = g.DT40;
+    s32 = (s40 + 128) >> 8;
+    X = vox_linear(g, q.w.i);
+    return true;
+}
+
+__device__ __forceinline__ void int_advance(const LatGrid &g, IntRay &q) {
+    int a = walk_exit_axis(q.w);
+    q.A -= q.dA[a];
+    if (!walk_step(g, q.w, a)) q.alive = false;
+}
+
+// Runs of consecutive lanes with the same key X (the whole wave takes part):
+// true on the last lane of each run, which receives the run's sum of s32
+// (a 64-bit prefix sum over the wave) and its length (from a max-scan of
+// the run heads).
+__device__ __forceinline__ bool wave_run(int64_t X, int64_t s32, int lane, int64_t &run_sum,
+                                         uint32_t &run_len) {
+    const int64_t Xp = __shfl_up(X, 1);
+    const int64_t Xn = __shfl_down(X, 1);
+    int head = (lane == 0 || Xp != X) ? lane : 0;
+    int64_t P = s32;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const int64_t tp = __shfl_up(P, d);
+        const int th = __shfl_up(head, d);
+        if (lane >= d) {
+            P += tp;
+            head = th > head ? th : head;
+        }
+    }
+    const int64_t before = __shfl(P, head > 0 ? head - 1 : 0);
+    run_sum = P - (head > 0 ? before : 0);
+    run_len = (uint32_t)(lane - head + 1);
+    return lane == 63 || Xn != X;
+}
+
+// the last lane of each run of equal keys (no sums)
+__device__ __forceinline__ bool wave_run_tail(int64_t X, int lane) {
+    const int64_t Xn = __shfl_down(X, 1);
+    return lane == 63 || Xn != X;
+}
+
+__device__ __forceinline__ void count_updates(int64_t updates, unsigned long long *n_updates) {
+    if (!n_updates) return;
+    // one atomic per wave
+    unsigned long long tot = (unsigned long long)updates;
+    for (int off = 32; off > 0; off >>= 1) tot += __shfl_xor(tot, off);
+    if ((threadIdx.x & 63) == 0 && tot) atomicAdd(n_updates, tot);
+}
+
+// Every lane of a wave takes each step together (the shuffles need the
+// whole wave); a finished lane keeps a voxel key of its own and adds
+// nothing.  Lanes on the same voxel in consecutive lanes (neighbouring
+// pixels) add their run's sum and count with one pair of atomics: integer
+// sums, so the totals do not depend on how the updates are grouped.
 __global__ void __launch_bounds__(256) k_integrate(LatGrid g, int64_t *__restrict__ sum,
                                                    uint32_t *__restrict__ cnt,
                                                    const float *__restrict__ o,
@@ -86,100 +193,133 @@ __global__ void __launch_bounds__(256) k_integrate(LatGrid g, int64_t *__restric
                                                    unsigned long long *n_updates) {
     const int64_t ray = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     const int lane = threadIdx.x & 63;
+    IntRay q;
+    int_begin(g, o, v, depth, n_rays, ray, q);
     int64_t updates = 0;
-    bool alive = false, surface = false;
-    LatRay r;
-    Walk w;
-    int64_t A = 0, DK = 0, dA[3] = {0, 0, 0};
-    if (ray < n_rays) {
-        float oo[3] = {o[3 * ray], o[3 * ray + 1], o[3 * ray + 2]};
-        float vv[3] = {v[3 * ray], v[3 * ray + 1], v[3 * ray + 2]};
-        float D = depth[ray];
-        int32_t inn, ind, outn, outd;
-        if (snap_ray(g, oo, vv, r) && grid_range(g, r, inn, ind, outn, outd) &&
-            walk_begin(g, r, inn, ind, w)) {
-            alive = true;
-            surface = isfinite(D) && D >= 1.52587890625e-05f && D < 4096.0f;
-            int64_t K = (int64_t)r.V[0] * r.V[0] + (int64_t)r.V[1] * r.V[1] +
-                        (int64_t)r.V[2] * r.V[2];
-            for (int a = 0; a < 3; ++a) {
-                int64_t C = g.LO[a] + (int64_t)w.i[a] * g.H + g.H / 2;
-                A += (int64_t)r.V[a] * (r.O[a] - C);
-                dA[a] = (int64_t)(r.V[a] < 0 ? -r.V[a] : r.V[a]) * g.H;
+    while (__any(q.alive)) {
+        int64_t X = -1 - lane, s32 = 0;
+        bool band = false;
+        const bool up = int_update(g, q, X, s32, band);
+        int64_t rs;
+        uint32_t rl;
+        const bool tail = wave_run(X, s32, lane, rs, rl);
+        if (up) {
+            if (tail) {
+                atomicAdd((unsigned long long *)&sum[X], (unsigned long long)rs);
+                atomicAdd(&cnt[X], rl);
             }
-            DK = surface ? depth_times_k(D, K - ((int64_t)1 << 40)) : 0;
-        }
-    }
-    const int64_t DT40 = g.DT40;
-    // every lane of the wave takes each step together (the shuffles below
-    // need the whole wave); a lane that has finished contributes nothing
-    while (__any(alive)) {
-        int64_t s32 = 0, X = -1 - lane;          // finished lanes: a voxel of their own
-        if (alive) {
-            int64_t s40 = surface ? A + DK : DT40;
-            if (s40 <= -DT40) {
-                alive = false;
-            } else {
-                if (s40 > DT40) s40 = DT40;
-                s32 = (s40 + 128) >> 8;           // units of 2^-32 m
-                X = vox_linear(g, w.i);
-            }
-        }
-        // runs of consecutive lanes on one voxel: the last lane of a run adds
-        // the run's sum and length (integer sums: the same totals in any order)
-        const int64_t Xp = __shfl_up(X, 1);
-        const int64_t Xn = __shfl_down(X, 1);
-        int head = (lane == 0 || Xp != X) ? lane : 0;
-        int64_t P = s32;
-#pragma unroll
-        for (int d = 1; d < 64; d <<= 1) {
-            const int64_t tp = __shfl_up(P, d);
-            const int th = __shfl_up(head, d);
-            if (lane >= d) {
-                P += tp;
-                head = th > head ? th : head;
-            }
-        }
-        const int64_t before = __shfl(P, head > 0 ? head - 1 : 0);
-        const bool tail = lane == 63 || Xn != X;
-        if (alive && tail) {
-            atomicAdd((unsigned long long *)&sum[X],
-                      (unsigned long long)(P - (head > 0 ? before : 0)));
-            atomicAdd(&cnt[X], (uint32_t)(lane - head + 1));
-        }
-        if (alive) {
             ++updates;
-            int a = walk_exit_axis(w);
-            A -= dA[a];
-            if (!walk_step(g, w, a)) alive = false;
+            int_advance(g, q);
         }
     }
-    if (n_updates) {
-        // one atomic per wave
-        unsigned long long tot = (unsigned long long)updates;
-        for (int off = 32; off > 0; off >>= 1) tot += __shfl_xor(tot, off);
-        if (lane == 0 && tot) atomicAdd(n_updates, tot);
+    count_updates(updates, n_updates);
+}
+
+// ------------------------------------------------- two-level volume ----
+//
+// Bricks of 8^3 voxels.  Per brick: one seen bit per voxel (8 words of 64
+// bits, word = z & 7, bit = 8 (y & 7) + (x & 7)), a band flag (some update
+// with s < D_T) and a pool slot; per-voxel sums and counts exist only in the
+// pool, for band bricks.  A brick outside the band received only updates
+// clamped to D_T, so its seen voxels hold V = D_T exactly and its others
+// are unseen: the two-level volume equals the dense one.
+
+struct BrickGrid {
+    int nb[3];
+};
+
+__device__ __forceinline__ int64_t brick_of(const BrickGrid &bg, const int32_t i[3]) {
+    return (int64_t)(i[0] >> 3) +
+           (int64_t)bg.nb[0] * ((int64_t)(i[1] >> 3) + (int64_t)bg.nb[1] * (i[2] >> 3));
+}
+__device__ __forceinline__ int local_of(const int32_t i[3]) {
+    return (i[0] & 7) | ((i[1] & 7) << 3) | ((i[2] & 7) << 6);
+}
+
+__global__ void __launch_bounds__(256) k_sparse_mark(LatGrid g, BrickGrid bg,
+                                                     unsigned long long *__restrict__ seen,
+                                                     uint32_t *__restrict__ band_flag,
+                                                     const float *__restrict__ o,
+                                                     const float *__restrict__ v,
+                                                     const float *__restrict__ depth,
+                                                     int64_t n_rays) {
+    const int64_t ray = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    const int lane = threadIdx.x & 63;
+    IntRay q;
+    int_begin(g, o, v, depth, n_rays, ray, q);
+    while (__any(q.alive)) {
+        int64_t X = -1 - lane, s32 = 0;
+        bool band = false;
+        const bool up = int_update(g, q, X, s32, band);
+        const bool tail = wave_run_tail(X, lane);
+        if (up) {
+            const int64_t b = brick_of(bg, q.w.i);
+            if (band) band_flag[b] = 1u;
+            if (tail)
+                atomicOr(&seen[b * 8 + (q.w.i[2] & 7)],
+                         1ull << ((q.w.i[1] & 7) * 8 + (q.w.i[0] & 7)));
+            int_advance(g, q);
+        }
     }
+}
+
+__global__ void __launch_bounds__(256) k_sparse_accum(LatGrid g, BrickGrid bg,
+                                                      const int32_t *__restrict__ slot, int64_t cap,
+                                                      int64_t *__restrict__ psum,
+                                                      uint32_t *__restrict__ pcnt,
+                                                      const float *__restrict__ o,
+                                                      const float *__restrict__ v,
+                                                      const float *__restrict__ depth,
+                                                      int64_t n_rays,
+                                                      unsigned long long *n_updates) {
+    const int64_t ray = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    const int lane = threadIdx.x & 63;
+    IntRay q;
+    int_begin(g, o, v, depth, n_rays, ray, q);
+    int64_t updates = 0;
+    while (__any(q.alive)) {
+        int64_t X = -1 - lane, s32 = 0;
+        bool band = false;
+        const bool up = int_update(g, q, X, s32, band);
+        int64_t rs;
+        uint32_t rl;
+        const bool tail = wave_run(X, s32, lane, rs, rl);
+        if (up) {
+            if (tail) {
+                const int32_t sl = slot[brick_of(bg, q.w.i)];
+                if (sl >= 0 && sl < cap) {
+                    const int64_t e = (int64_t)sl * 512 + local_of(q.w.i);
+                    atomicAdd((unsigned long long *)&psum[e], (unsigned long long)rs);
+                    atomicAdd(&pcnt[e], rl);
+                }
+            }
+            ++updates;
+            int_advance(g, q);
+        }
+    }
+    count_updates(updates, n_updates);
 }
 
 // ------------------------------------------------------------- finalize ----
 
 // bit0 = V <= D_s, bit2 = V < 0 (scratch for the erosion passes)
+__device__ __forceinline__ float voxel_value(const LatGrid &g, int64_t sum, uint32_t c) {
+    if (c == 0) return -g.d_t;
+    float s = (float)sum * 2.3283064365386963e-10f;  // 2^-32
+    return s / (float)c;
+}
+__device__ __forceinline__ uint8_t voxel_flags(const LatGrid &g, float val) {
+    return (uint8_t)((val <= g.d_s ? 1u : 0u) | (val < 0.0f ? 4u : 0u));
+}
+
 __global__ void k_finalize(LatGrid g, const int64_t *__restrict__ sum,
                            const uint32_t *__restrict__ cnt, float *__restrict__ V,
                            uint8_t *__restrict__ flags, int64_t N) {
     int64_t X = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (X >= N) return;
-    uint32_t c = cnt[X];
-    float val;
-    if (c == 0) {
-        val = -g.d_t;
-    } else {
-        float s = (float)sum[X] * 2.3283064365386963e-10f;  // 2^-32
-        val = s / (float)c;
-    }
+    const float val = voxel_value(g, sum[X], cnt[X]);
     if (V) V[X] = val;
-    flags[X] = (uint8_t)((val <= g.d_s ? 1u : 0u) | (val < 0.0f ? 4u : 0u));
+    flags[X] = voxel_flags(g, val);
 }
 
 // Erosion of the "negative" bit along one axis: bit `dst` of a voxel is the
@@ -207,6 +347,116 @@ __global__ void k_erode(LatGrid g, uint8_t *flags, int axis, int src, int dst, i
 __global__ void k_flags_clean(uint8_t *flags, int64_t N) {
     int64_t X = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (X < N) flags[X] &= 3u;
+}
+
+// Two-level volume, finalized to the dense V and flags: a voxel of a band
+// brick takes the value of its pool sums; elsewhere a seen voxel holds D_T
+// and an unseen one -D_T.  One thread per voxel of an xy slice, slice z =
+// blockIdx.y.
+__global__ void k_sparse_finalize(LatGrid g, BrickGrid bg,
+                                  const unsigned long long *__restrict__ seen,
+                                  const int32_t *__restrict__ slot, int64_t cap,
+                                  const int64_t *__restrict__ psum,
+                                  const uint32_t *__restrict__ pcnt, float *__restrict__ V,
+                                  uint8_t *__restrict__ flags) {
+    const int64_t nxy = (int64_t)g.n[0] * g.n[1];
+    const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (p >= nxy) return;
+    const int32_t i[3] = {(int32_t)(p % g.n[0]), (int32_t)(p / g.n[0]), (int32_t)blockIdx.y};
+    const int64_t X = p + nxy * i[2];
+    const int64_t b = brick_of(bg, i);
+    const int32_t sl = slot[b];
+    float val;
+    if (sl >= 0 && sl < cap) {
+        const int64_t e = (int64_t)sl * 512 + local_of(i);
+        val = voxel_value(g, psum[e], pcnt[e]);
+    } else {
+        const bool s = (seen[b * 8 + (i[2] & 7)] >> ((i[1] & 7) * 8 + (i[0] & 7))) & 1ull;
+        val = s ? g.d_t : -g.d_t;
+    }
+    if (V) V[X] = val;
+    flags[X] = voxel_flags(g, val);
+}
+
+// Pool slots of the band bricks, in ascending brick order: per-block counts,
+// one scan of the block totals, per-block placement (slot -1 elsewhere).
+constexpr int kBrickBlock = 256;
+
+__device__ __forceinline__ int brick_block_scan(int x, int *lds4, int *total) {
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    int inc = x;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        int y = __shfl_up(inc, off);
+        if (lane >= off) inc += y;
+    }
+    if (lane == 63) lds4[wv] = inc;
+    __syncthreads();
+    int before = 0, tot = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int t = lds4[k];
+        if (k < wv) before += t;
+        tot += t;
+    }
+    __syncthreads();
+    *total = tot;
+    return before + inc - x;
+}
+
+__global__ void __launch_bounds__(kBrickBlock) k_brick_count(const uint32_t *__restrict__ band,
+                                                             int64_t nbr,
+                                                             int64_t *__restrict__ block_sum) {
+    __shared__ int lds4[4];
+    const int64_t b = blockIdx.x * (int64_t)kBrickBlock + threadIdx.x;
+    int tot;
+    brick_block_scan(b < nbr && band[b] ? 1 : 0, lds4, &tot);
+    if (threadIdx.x == 0) block_sum[blockIdx.x] = tot;
+}
+
+// exclusive scan of the block totals in one 1024-thread block; *n = total
+__global__ void __launch_bounds__(1024) k_brick_scan(const int64_t *__restrict__ block_sum,
+                                                     int64_t nb, int64_t *__restrict__ block_off,
+                                                     int64_t *__restrict__ n) {
+    __shared__ int64_t wsum[16];
+    __shared__ int64_t carry;
+    if (threadIdx.x == 0) carry = 0;
+    __syncthreads();
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    for (int64_t base = 0; base < nb; base += 1024) {
+        const int64_t i = base + threadIdx.x;
+        const int64_t x = i < nb ? block_sum[i] : 0;
+        int64_t inc = x;
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            int64_t y = __shfl_up(inc, off);
+            if (lane >= off) inc += y;
+        }
+        if (lane == 63) wsum[wv] = inc;
+        __syncthreads();
+        int64_t before = carry, tot = 0;
+        for (int k = 0; k < 16; ++k) {
+            if (k < wv) before += wsum[k];
+            tot += wsum[k];
+        }
+        if (i < nb) block_off[i] = before + inc - x;
+        __syncthreads();
+        if (threadIdx.x == 0) carry += tot;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *n = carry;
+}
+
+__global__ void __launch_bounds__(kBrickBlock) k_brick_place(const uint32_t *__restrict__ band,
+                                                             int64_t nbr,
+                                                             const int64_t *__restrict__ block_off,
+                                                             int32_t *__restrict__ slot) {
+    __shared__ int lds4[4];
+    const int64_t b = blockIdx.x * (int64_t)kBrickBlock + threadIdx.x;
+    const int x = b < nbr && band[b] ? 1 : 0;
+    int tot;
+    const int ex = brick_block_scan(x, lds4, &tot);
+    if (b < nbr) slot[b] = x ? (int32_t)(block_off[blockIdx.x] + ex) : -1;
 }
 
 // --------------------------------------------------------------- bounds ----
@@ -341,6 +591,40 @@ __global__ void __launch_bounds__(256) k_bound_stats(const float *__restrict__ t
     }
 }
 
+// bit1 of the flags from bit2 (V < 0): the (2r+1)^3 erosion as three axis
+// passes, then the scratch bits cleared
+static void erode_flags(const LatGrid &g, uint8_t *flags, int64_t N, hipStream_t s) {
+    unsigned nb = blocks_for(N, 256);
+    hipLaunchKernelGGL(k_erode, dim3(nb), dim3(256), 0, s, g, flags, 0, 2, 3, N);
+    hipLaunchKernelGGL(k_erode, dim3(nb), dim3(256), 0, s, g, flags, 1, 3, 4, N);
+    hipLaunchKernelGGL(k_erode, dim3(nb), dim3(256), 0, s, g, flags, 2, 4, 1, N);
+    hipLaunchKernelGGL(k_flags_clean, dim3(nb), dim3(256), 0, s, flags, N);
+}
+
+// Brick grid of the two-level volume and its metadata layout: seen words
+// [n_bricks][8] (u64), band flags [n_bricks] (u32), pool slots [n_bricks]
+// (int32).
+struct SparseMeta {
+    unsigned long long *seen;
+    uint32_t *band;
+    int32_t *slot;
+};
+static int sparse_dims(const tsdfs_grid *grid, LatGrid *g, BrickGrid *bg, int64_t *nbr) {
+    int rc = make_lat_grid(grid, g);
+    if (rc) return rc;
+    for (int a = 0; a < 3; ++a) bg->nb[a] = (g->n[a] + 7) / 8;
+    *nbr = (int64_t)bg->nb[0] * bg->nb[1] * bg->nb[2];
+    return TSDFS_OK;
+}
+static SparseMeta sparse_meta(void *meta, int64_t nbr) {
+    SparseMeta m;
+    m.seen = (unsigned long long *)meta;
+    m.band = (uint32_t *)(m.seen + 8 * nbr);
+    m.slot = (int32_t *)(m.band + nbr);
+    return m;
+}
+constexpr size_t kPoolBrickBytes = 512 * (sizeof(int64_t) + sizeof(uint32_t));
+
 }  // namespace tsdfs
 
 using namespace tsdfs;
@@ -400,10 +684,7 @@ int tsdf_finalize(const tsdfs_grid *grid, const void *state, float *V, uint8_t *
     hipStream_t s = as_stream(stream);
     unsigned nb = blocks_for(N, 256);
     hipLaunchKernelGGL(k_finalize, dim3(nb), dim3(256), 0, s, g, sum, cnt, V, flags, N);
-    hipLaunchKernelGGL(k_erode, dim3(nb), dim3(256), 0, s, g, flags, 0, 2, 3, N);
-    hipLaunchKernelGGL(k_erode, dim3(nb), dim3(256), 0, s, g, flags, 1, 3, 4, N);
-    hipLaunchKernelGGL(k_erode, dim3(nb), dim3(256), 0, s, g, flags, 2, 4, 1, N);
-    hipLaunchKernelGGL(k_flags_clean, dim3(nb), dim3(256), 0, s, flags, N);
+    erode_flags(g, flags, N, s);
     TSDFS_LAUNCH_CHECK();
     return TSDFS_OK;
 }
@@ -459,4 +740,144 @@ int tsdf_bound_stats(const float *t_in, const float *t_out, const float *t_n, co
     return TSDFS_OK;
 }
 
+int tsdf_sparse_meta_bytes(const tsdfs_grid *grid, size_t *bytes) {
+    LatGrid g;
+    BrickGrid bg;
+    int64_t nbr;
+    int rc = sparse_dims(grid, &g, &bg, &nbr);
+    if (rc) return rc;
+    TSDFS_CHECK_ARG(bytes != nullptr, "bytes is NULL");
+    *bytes = (size_t)nbr * (8 * sizeof(unsigned long long) + sizeof(uint32_t) + sizeof(int32_t));
+    return TSDFS_OK;
+}
+
+int tsdf_sparse_reset(const tsdfs_grid *grid, void *meta, void *stream) {
+    size_t bytes;
+    int rc = tsdf_sparse_meta_bytes(grid, &bytes);
+    if (rc) return rc;
+    TSDFS_CHECK_ARG(meta != nullptr, "meta is NULL");
+    const int64_t words = (int64_t)(bytes / 4);
+    hipLaunchKernelGGL(k_zero_u32, dim3(std::min<int64_t>(blocks_for(words, 256), 65536)),
+                       dim3(256), 0, as_stream(stream), (uint32_t *)meta, words);
+    TSDFS_LAUNCH_CHECK();
+    return TSDFS_OK;
+}
+
+int tsdf_sparse_mark(const tsdfs_grid *grid, void *meta, const float *o, const float *v,
+                     const float *depth, int64_t n_rays, void *stream) {
+    LatGrid g;
+    BrickGrid bg;
+    int64_t nbr;
+    int rc = sparse_dims(grid, &g, &bg, &nbr);
+    if (rc) return rc;
+    TSDFS_CHECK_ARG(n_rays >= 0, "n_rays must be >= 0");
+    if (n_rays == 0) return TSDFS_OK;
+    TSDFS_CHECK_ARG(meta && o && v && depth, "NULL array argument");
+    SparseMeta m = sparse_meta(meta, nbr);
+    hipLaunchKernelGGL(k_sparse_mark, dim3(blocks_for(n_rays, 256)), dim3(256), 0,
+                       as_stream(stream), g, bg, m.seen, m.band, o, v, depth, n_rays);
+    TSDFS_LAUNCH_CHECK();
+    return TSDFS_OK;
+}
+
+int tsdf_sparse_alloc_ws_bytes(const tsdfs_grid *grid, size_t *bytes) {
+    LatGrid g;
+    BrickGrid bg;
+    int64_t nbr;
+    int rc = sparse_dims(grid, &g, &bg, &nbr);
+    if (rc) return rc;
+    TSDFS_CHECK_ARG(bytes != nullptr, "bytes is NULL");
+    *bytes = (size_t)(2 * (int64_t)blocks_for(nbr, kBrickBlock) + 1) * sizeof(int64_t);
+    return TSDFS_OK;
+}
+
+int tsdf_sparse_alloc(const tsdfs_grid *grid, void *meta, int64_t *n_band_dev, void *ws,
+                      size_t ws_bytes, void *stream) {
+    LatGrid g;
+    BrickGrid bg;
+    int64_t nbr;
+    int rc = sparse_dims(grid, &g, &bg, &nbr);
+    if (rc) return rc;
+    TSDFS_CHECK_ARG(meta && n_band_dev, "NULL argument");
+    size_t need;
+    tsdf_sparse_alloc_ws_bytes(grid, &need);
+    TSDFS_CHECK_ARG(ws && ws_bytes >= need, "workspace too small (%zu < %zu)", ws_bytes, need);
+    SparseMeta m = sparse_meta(meta, nbr);
+    hipStream_t st = as_stream(stream);
+    const int64_t nb = blocks_for(nbr, kBrickBlock);
+    int64_t *block_sum = (int64_t *)ws, *block_off = block_sum + nb;
+    hipLaunchKernelGGL(k_brick_count, dim3(nb), dim3(kBrickBlock), 0, st, m.band, nbr, block_sum);
+    hipLaunchKernelGGL(k_brick_scan, dim3(1), dim3(1024), 0, st, block_sum, nb, block_off,
+                       n_band_dev);
+    hipLaunchKernelGGL(k_brick_place, dim3(nb), dim3(kBrickBlock), 0, st, m.band, nbr, block_off,
+                       m.slot);
+    TSDFS_LAUNCH_CHECK();
+    return TSDFS_OK;
+}
+
+int tsdf_sparse_pool_bytes(int64_t cap, size_t *bytes) {
+    TSDFS_CHECK_ARG(cap >= 0 && cap < ((int64_t)1 << 31), "cap must be in [0, 2^31)");
+    TSDFS_CHECK_ARG(bytes != nullptr, "bytes is NULL");
+    *bytes = (size_t)cap * kPoolBrickBytes;
+    return TSDFS_OK;
+}
+
+int tsdf_sparse_pool_reset(int64_t cap, void *pool, void *stream) {
+    size_t bytes;
+    int rc = tsdf_sparse_pool_bytes(cap, &bytes);
+    if (rc) return rc;
+    if (cap == 0) return TSDFS_OK;
+    TSDFS_CHECK_ARG(pool != nullptr, "pool is NULL");
+    const int64_t words = (int64_t)(bytes / 4);
+    hipLaunchKernelGGL(k_zero_u32, dim3(std::min<int64_t>(blocks_for(words, 256), 65536)),
+                       dim3(256), 0, as_stream(stream), (uint32_t *)pool, words);
+    TSDFS_LAUNCH_CHECK();
+    return TSDFS_OK;
+}
+
+int tsdf_sparse_accumulate(const tsdfs_grid *grid, const void *meta, void *pool, int64_t cap,
+                           const float *o, const float *v, const float *depth, int64_t n_rays,
+                           int64_t *n_updates_dev, void *stream) {
+    LatGrid g;
+    BrickGrid bg;
+    int64_t nbr;
+    int rc = sparse_dims(grid, &g, &bg, &nbr);
+    if (rc) return rc;
+    TSDFS_CHECK_ARG(n_rays >= 0, "n_rays must be >= 0");
+    TSDFS_CHECK_ARG(cap >= 0 && cap < ((int64_t)1 << 31), "cap must be in [0, 2^31)");
+    if (n_rays == 0) return TSDFS_OK;
+    TSDFS_CHECK_ARG(meta && o && v && depth && (pool || cap == 0), "NULL array argument");
+    SparseMeta m = sparse_meta((void *)meta, nbr);
+    int64_t *psum = (int64_t *)pool;
+    uint32_t *pcnt = (uint32_t *)(psum + 512 * cap);
+    hipLaunchKernelGGL(k_sparse_accum, dim3(blocks_for(n_rays, 256)), dim3(256), 0,
+                       as_stream(stream), g, bg, m.slot, cap, psum, pcnt, o, v, depth, n_rays,
+                       (unsigned long long *)n_updates_dev);
+    TSDFS_LAUNCH_CHECK();
+    return TSDFS_OK;
+}
+
+int tsdf_sparse_finalize(const tsdfs_grid *grid, const void *meta, const void *pool, int64_t cap,
+                         float *V, uint8_t *flags, void *stream) {
+    LatGrid g;
+    BrickGrid bg;
+    int64_t nbr;
+    int rc = sparse_dims(grid, &g, &bg, &nbr);
+    if (rc) return rc;
+    TSDFS_CHECK_ARG(cap >= 0 && cap < ((int64_t)1 << 31), "cap must be in [0, 2^31)");
+    TSDFS_CHECK_ARG(meta && flags && (pool || cap == 0), "NULL array argument");
+    TSDFS_CHECK_ARG(g.n[2] <= 65535, "the two-level volume needs n[2] <= 65535");
+    SparseMeta m = sparse_meta((void *)meta, nbr);
+    const int64_t *psum = (const int64_t *)pool;
+    const uint32_t *pcnt = (const uint32_t *)(psum + 512 * cap);
+    hipStream_t s = as_stream(stream);
+    const int64_t nxy = (int64_t)g.n[0] * g.n[1];
+    hipLaunchKernelGGL(k_sparse_finalize, dim3(blocks_for(nxy, 256), g.n[2]), dim3(256), 0, s, g,
+                       bg, m.seen, m.slot, cap, psum, pcnt, V, flags);
+    erode_flags(g, flags, n_vox(g), s);
+    TSDFS_LAUNCH_CHECK();
+    return TSDFS_OK;
+}
+
 }  // extern "C"
+

@@ -74,6 +74,60 @@ def finalize(g, st, want_v=True):
     return V, fl
 
 
+def sparse_integrate(g, batches, n_updates=None):
+    """Two-level volume from the rays of `batches` (a list of (o, v, depth)
+    device tensors): reset, mark every batch, allocate the band bricks (one
+    host read of their number), then accumulate every batch into a pool of
+    exactly that many bricks.  Returns dict(meta, pool, n_band)."""
+    d = _dev()
+    lib = L.load()
+    b = ctypes.c_size_t(0)
+    L.check(lib.tsdf_sparse_meta_bytes(ctypes.byref(g), ctypes.byref(b)))
+    meta = torch.empty(b.value, dtype=torch.uint8, device=d)
+    L.check(lib.tsdf_sparse_reset(ctypes.byref(g), _p(meta), _stream()))
+    for o, v, depth in batches:
+        L.check(lib.tsdf_sparse_mark(ctypes.byref(g), _p(meta), _p(o), _p(v), _p(depth),
+                                     o.shape[0], _stream()))
+    L.check(lib.tsdf_sparse_alloc_ws_bytes(ctypes.byref(g), ctypes.byref(b)))
+    ws = torch.empty(b.value, dtype=torch.uint8, device=d)
+    n_band = torch.zeros(1, dtype=torch.int64, device=d)
+    L.check(lib.tsdf_sparse_alloc(ctypes.byref(g), _p(meta), _p(n_band), _p(ws), ws.numel(),
+                                  _stream()))
+    cap = int(n_band.item())
+    L.check(lib.tsdf_sparse_pool_bytes(cap, ctypes.byref(b)))
+    pool = torch.empty(max(b.value, 8), dtype=torch.uint8, device=d)
+    L.check(lib.tsdf_sparse_pool_reset(cap, _p(pool), _stream()))
+    for o, v, depth in batches:
+        L.check(lib.tsdf_sparse_accumulate(ctypes.byref(g), _p(meta), _p(pool), cap, _p(o), _p(v),
+                                           _p(depth), o.shape[0], _p(n_updates), _stream()))
+    return dict(meta=meta, pool=pool, n_band=cap)
+
+
+def sparse_views(g, sp):
+    """seen words [n_bricks, 8] int64 (bit patterns), band [n_bricks] int32,
+    slot [n_bricks] int32, pool sums [cap, 512] int64 and counts [cap, 512]
+    int32 (uint32 bit patterns) of a two-level volume; bricks x fastest."""
+    nb = [(int(x) + 7) // 8 for x in g.n]
+    nbr = nb[0] * nb[1] * nb[2]
+    m = sp["meta"]
+    seen = m[: 64 * nbr].view(torch.int64).view(nbr, 8)
+    band = m[64 * nbr: 68 * nbr].view(torch.int32)
+    slot = m[68 * nbr: 72 * nbr].view(torch.int32)
+    cap = sp["n_band"]
+    psum = sp["pool"][: 4096 * cap].view(torch.int64).view(cap, 512)
+    pcnt = sp["pool"][4096 * cap: 6144 * cap].view(torch.int32).view(cap, 512)
+    return dict(seen=seen, band=band, slot=slot, psum=psum, pcnt=pcnt, n_bricks=tuple(nb))
+
+
+def sparse_finalize(g, sp, want_v=True):
+    N = n_voxels(g)
+    V = torch.empty(N, dtype=torch.float32, device=_dev()) if want_v else None
+    fl = torch.empty(N, dtype=torch.uint8, device=_dev())
+    L.check(L.load().tsdf_sparse_finalize(ctypes.byref(g), _p(sp["meta"]), _p(sp["pool"]),
+                                          sp["n_band"], _p(V), _p(fl), _stream()))
+    return V, fl
+
+
 def ray_bounds(g, flags, o, v, t_far=float("inf"), steps=False):
     R = o.shape[0]
     d = _dev()
