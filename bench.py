@@ -132,6 +132,8 @@ def main():
                     help="fine samples per ray of the coarse + fine leg (0: skip the leg)")
     ap.add_argument("--fill-rounds", type=int, default=2,
                     help="rounds of filling unseen voxels on a copy of the volume (0: skip)")
+    ap.add_argument("--no-two-level", dest="two_level", action="store_false",
+                    help="skip the two-level volume leg")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a device-to-device copy of MIB MiB (to scale HBM counters)")
     args = ap.parse_args()
@@ -531,6 +533,59 @@ def main():
         }
         log(f"fill unseen: {rounds}; render after {ms_fl:.3f} ms/step")
         del Rf, fr
+
+    # ---- two-level volume (bricks of 8^3 voxels; integration sums only
+    # where the truncation band reaches) of the room at this grid's
+    # resolution and with 4x finer voxels: time, memory against the dense
+    # state, flags checked equal to the dense volume's, and the bounds of the
+    # view on each resolution
+    if args.two_level:
+        from dataclasses import replace as _replace
+        tl = {}
+        o_b = [(o_d, v_d, d_d)]
+        for fac in (1, 4):
+            gg = g if fac == 1 else _replace(g, n=tuple(x * fac for x in g.n), h=g.h / fac,
+                                             d_t=g.d_t / fac, d_s=g.d_s / fac)
+            grid_t = ops.make_grid(gg.n, gg.lo, gg.h, gg.d_t, gg.d_s, gg.nb_radius, gg.m_consec)
+            ops.sparse_integrate(grid_t, o_b)                     # warm-up
+            torch.cuda.synchronize()
+            e0.record()
+            sp = ops.sparse_integrate(grid_t, o_b)
+            e1.record()
+            torch.cuda.synchronize()
+            t_int = e0.elapsed_time(e1)
+            e0.record()
+            _, fl_t = ops.sparse_finalize(grid_t, sp, want_v=False)
+            e1.record()
+            torch.cuda.synchronize()
+            t_fin = e0.elapsed_time(e1)
+            st_t = ops.new_state(grid_t)
+            torch.cuda.synchronize()
+            e0.record()
+            ops.integrate(grid_t, st_t, o_d, v_d, d_d)
+            e1.record()
+            torch.cuda.synchronize()
+            t_dense = e0.elapsed_time(e1)
+            _, fl_dense = ops.finalize(grid_t, st_t, want_v=False)
+            same = bool(torch.equal(fl_t, fl_dense))
+            del st_t, fl_dense
+            bt = ops.ray_bounds(grid_t, fl_t, ro_d, rv_d, s.t_far)
+            hit = bt["status"] == 0
+            nbr = sp["meta"].numel() // 72
+            tl[f"{gg.n[0]}^3"] = {
+                "h_m": gg.h, "bricks": nbr, "band_bricks": sp["n_band"],
+                "band_frac": sp["n_band"] / nbr,
+                "two_level_bytes": sp["meta"].numel() + sp["pool"].numel(),
+                "dense_state_bytes": 12 * gg.n_vox, "flag_bytes": gg.n_vox,
+                "integrate_ms": t_int, "finalize_ms": t_fin, "dense_integrate_ms": t_dense,
+                "flags_equal_dense": same,
+                "mean_bound_m": float((bt["t_f"] - bt["t_n"])[hit].mean().item()),
+                "mean_bound_voxels": float(bt["n_vox"][hit].float().mean().item()),
+            }
+            del sp, fl_t, bt
+            torch.cuda.empty_cache()
+        result["two_level"] = tl
+        log(f"two-level volume: {tl}")
 
     if not args.no_hs:
         for _ in range(1):
