@@ -119,7 +119,8 @@ def main():
     ap.add_argument("--workload", default="c2")
     ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16"])
     ap.add_argument("--hs-steps", type=int, default=2)
-    ap.add_argument("--cpu-rays", type=int, default=1024)
+    ap.add_argument("--cpu-rays", type=int, default=16384,
+                    help="rays of the view in the CPU oracle sample (about 10-30 s of host work)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-hs", action="store_true")
     ap.add_argument("--no-other", action="store_true", help="skip the other-precision leg")
