@@ -281,6 +281,27 @@ def main():
         },
     }
 
+    # ---- sampling density swept over the paper's 13-28 samples per ray:
+    # rho samples per traversed voxel (the default rho is the main step)
+    sweep = {}
+    rho0 = R.rho
+    for num, den in ((1, 3), (rho0[0], rho0[1]), (5, 8), (5, 7)):
+        R.rho = (num, den)
+        for _ in range(args.warmup):
+            R.render(ro_d, rv_d)
+        torch.cuda.synchronize()
+        start.record()
+        for _ in range(args.steps):
+            out_s = R.render(ro_d, rv_d)
+        end.record()
+        torch.cuda.synchronize()
+        ms_s = start.elapsed_time(end) / args.steps
+        sweep[f"{num}/{den}"] = {"ms_per_step": ms_s, "rays_per_s": n_rays / (ms_s * 1e-3),
+                                 "samples_per_ray": int(out_s["s_total"].item()) / n_rays}
+    R.rho = rho0
+    result["rho_sweep"] = sweep
+    log(f"rho sweep: {sweep}")
+
     # ---- the other precision on the same step
     other = _lib.FP32 if prec == _lib.BF16 else _lib.BF16
     if args.no_other:
@@ -583,6 +604,24 @@ def main():
                 "mean_bound_m": float((bt["t_f"] - bt["t_n"])[hit].mean().item()),
                 "mean_bound_voxels": float(bt["n_vox"][hit].float().mean().item()),
             }
+            if fac > 1:
+                # the view rendered on the finer flags (same field, same rules)
+                Rt = TsdfRenderer(grid_t, field, s.rho_num, s.rho_den, s.n_min, s.n_max,
+                                  cfg.neus_s, s.t_far, prec)
+                Rt.flags = fl_t
+                for _ in range(args.warmup):
+                    Rt.render(ro_d, rv_d)
+                torch.cuda.synchronize()
+                start.record()
+                for _ in range(args.steps):
+                    out_t = Rt.render(ro_d, rv_d)
+                end.record()
+                torch.cuda.synchronize()
+                ms_t = start.elapsed_time(end) / args.steps
+                tl[f"{gg.n[0]}^3"].update(
+                    render_ms_per_step=ms_t, render_rays_per_s=n_rays / (ms_t * 1e-3),
+                    render_samples_per_ray=int(out_t["s_total"].item()) / n_rays)
+                del Rt, out_t
             del sp, fl_t, bt
             torch.cuda.empty_cache()
         result["two_level"] = tl
@@ -606,6 +645,8 @@ def main():
             "speedup_tsdf_vs_hs": hs_ms / ms,
             "speedup_full_vs_hs": hs_ms / full_ms if full_ms else None,
         }
+        for v_ in result["rho_sweep"].values():
+            v_["speedup_vs_hs"] = hs_ms / v_["ms_per_step"]
         log(f"hs 64+64: {hs_ms:.2f} ms/step")
 
     if not args.no_cpu_baseline:
