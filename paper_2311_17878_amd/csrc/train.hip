@@ -80,11 +80,47 @@ static rocblas_status gemm_rm(const Gemm &g, bool ta, bool tb, int M, int N, int
                            rocblas_gemm_algo_standard, 0, 0);
 }
 
-// y[N] += sum over rows of row-major A[R,N] (ld)
-static rocblas_status colsum(rocblas_handle h, int R, int N, const float *A, int ld,
-                             const float *ones, float *y) {
-    const float one = 1.0f;
-    return rocblas_sgemv(h, rocblas_operation_none, N, R, &one, A, ld, ones, 1, &one, y, 1);
+// y[N] += sum over the rows of row-major A[R,N] (ld): per block of 64
+// columns and chunk of kColsumChunk rows a partial sum (four row phases,
+// coalesced row reads, combined in LDS), then the chunks summed in order,
+// so the result does not depend on scheduling.  part: [ceil(R/chunk)][N].
+constexpr int kColsumChunk = 1024;
+
+__global__ void __launch_bounds__(256) k_colsum_part(const float *__restrict__ A, int R, int N,
+                                                     int ld, float *__restrict__ part) {
+    __shared__ float red[4][64];
+    const int c = threadIdx.x & 63, ph = threadIdx.x >> 6;
+    const int j = blockIdx.x * 64 + c;
+    const int64_t r0 = (int64_t)blockIdx.y * kColsumChunk;
+    const int64_t r1 = r0 + kColsumChunk < R ? r0 + kColsumChunk : R;
+    float s = 0.0f;
+    if (j < N)
+        for (int64_t r = r0 + ph; r < r1; r += 4) s += A[r * ld + j];
+    red[ph][c] = s;
+    __syncthreads();
+    if (ph == 0 && j < N)
+        part[(int64_t)blockIdx.y * N + j] = (red[0][c] + red[1][c]) + (red[2][c] + red[3][c]);
+}
+
+__global__ void k_colsum_fin(const float *__restrict__ part, int n_chunks, int N,
+                             float *__restrict__ y) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= N) return;
+    float s = 0.0f;
+    for (int c = 0; c < n_chunks; ++c) s += part[(int64_t)c * N + j];
+    y[j] += s;
+}
+
+static int colsum_chunks(int R) { return (R + kColsumChunk - 1) / kColsumChunk; }
+
+static rocblas_status colsum(hipStream_t st, int R, int N, const float *A, int ld, float *part,
+                             float *y) {
+    if (R <= 0 || N <= 0) return rocblas_status_success;
+    const int nch = colsum_chunks(R);
+    hipLaunchKernelGGL(k_colsum_part, dim3((N + 63) / 64, nch), dim3(256), 0, st, A, R, N, ld,
+                       part);
+    hipLaunchKernelGGL(k_colsum_fin, dim3((N + 255) / 256), dim3(256), 0, st, part, nch, N, y);
+    return hipGetLastError() == hipSuccess ? rocblas_status_success : rocblas_status_internal_error;
 }
 
 // ------------------------------------------------------------- compositing --
@@ -184,7 +220,7 @@ struct BwdBufs {
     float *Ybar;                           // [R, 1 + n_feat]
     float *T0, *T1, *T2, *T3;             // scratch [R, max(cin, W+1)]
     float *Z2[kMaxHidden];                 // second-order contributions
-    float *ones;                           // [R]
+    float *part;                           // column-sum partials [ceil(R/1024)][wide]
     float *loss;                           // [2] eikonal loss (device)
     __bf16 *ca, *cb;                       // BF16 copies of product inputs [bf16_cap]
     size_t bf16_cap;
@@ -233,7 +269,7 @@ static size_t carve(BwdBufs &b, const tsdfs_field *F, int R, char *base) {
     b.T1 = take((size_t)R * wide);
     b.T2 = take((size_t)R * wide);
     b.T3 = take((size_t)R * wide);
-    b.ones = take((size_t)R);
+    b.part = take((size_t)colsum_chunks(R) * wide);
     b.loss = take(2);
     // every product input is an [R or <= 272 rows][<= 272] row-major block
     b.bf16_cap = (size_t)(R > kMaxRows ? R : kMaxRows) * (kMaxRows + 8);
@@ -286,9 +322,9 @@ static int network_backward(tsdfs_field *F, const float *o, const float *v, cons
     auto gW = [&](int l) { return gs + F->w_off[l]; };
     auto gb = [&](int l) { return gs + F->b_off[l]; };
 
-    // ---- inputs: x_hat, direction, encoding and its Jacobian; ones; loss = 0
+    // ---- inputs: x_hat, direction, encoding and its Jacobian; loss = 0
     {
-        float *xh = B.xh, *vr = B.vr, *gam = B.gam, *J = B.J, *ones = B.ones, *loss = B.loss;
+        float *xh = B.xh, *vr = B.vr, *gam = B.gam, *J = B.J, *loss = B.loss;
         const int Si = (int)S;
         map((int64_t)R, st, [=] __device__(int64_t r) {
             float p[3], vv[3];
@@ -323,7 +359,6 @@ static int network_backward(tsdfs_field *F, const float *o, const float *v, cons
                     J[(int64_t)r * dg + j] = rem < 3 ? sc * cosf(y) : -sc * sinf(y);
                 }
             }
-            ones[r] = 1.0f;
             if (r < 2) loss[r] = 0.0f;
         });
     }
@@ -447,7 +482,7 @@ static int network_backward(tsdfs_field *F, const float *o, const float *v, cons
     }
     // dW_c4 += dz^T H3 ; db += sum dz ; dH3 = dz W_c4
     BLAS(gemm_rm(G, true, false, 3, W, R, 1.0f, B.T0, 3, B.Hc[nc - 1], W, 1.0f, gc + F->cw_off[nc], W));
-    BLAS(colsum(h, R, 3, B.T0, 3, B.ones, gc + F->cb_off[nc]));
+    BLAS(colsum(st, R, 3, B.T0, 3, B.part, gc + F->cb_off[nc]));
     BLAS(gemm_rm(G, false, false, R, W, 3, 1.0f, B.T0, 3, Wc + F->cw_off[nc], W, 0.0f, B.T1, W));
     for (int l = nc - 1; l >= 0; --l) {
         const int in = F->cdin[l];
@@ -456,7 +491,7 @@ static int network_backward(tsdfs_field *F, const float *o, const float *v, cons
         map((int64_t)R * W, st, [=] __device__(int64_t i) { dZ[i] = Z[i] > 0.0f ? dH[i] : 0.0f; });
         const float *X = l == 0 ? B.Cin : B.Hc[l - 1];
         BLAS(gemm_rm(G, true, false, W, in, R, 1.0f, dZ, W, X, in, 1.0f, gc + F->cw_off[l], in));
-        BLAS(colsum(h, R, W, dZ, W, B.ones, gc + F->cb_off[l]));
+        BLAS(colsum(st, R, W, dZ, W, B.part, gc + F->cb_off[l]));
         // dX = dZ W_c : [R, in] (into T1, ld = in)
         BLAS(gemm_rm(G, false, false, R, in, W, 1.0f, dZ, W, Wc + F->cw_off[l], in, 0.0f, B.T1, in));
     }
@@ -521,7 +556,7 @@ static int network_backward(tsdfs_field *F, const float *o, const float *v, cons
         });
         if (top) {
             // w_f_bar += column sums of delta_bar * softplus'(z)
-            BLAS(colsum(h, R, out, B.T1, W, B.ones, gW(nh)));
+            BLAS(colsum(st, R, out, B.T1, W, B.part, gW(nh)));
             break;
         }
         const int ln = l + 1;
@@ -545,7 +580,7 @@ static int network_backward(tsdfs_field *F, const float *o, const float *v, cons
     // ---- first-order pass (ordinary backprop of the forward, with the
     // second-order contributions Z2 injected at every hidden layer)
     BLAS(gemm_rm(G, true, false, ny, W, R, 1.0f, B.Ybar, ny, B.X[nh], W, 1.0f, gW(nh), W));
-    BLAS(colsum(h, R, ny, B.Ybar, ny, B.ones, gb(nh)));
+    BLAS(colsum(st, R, ny, B.Ybar, ny, B.part, gb(nh)));
     BLAS(gemm_rm(G, false, false, R, W, ny, 1.0f, B.Ybar, ny, Wl(nh), W, 0.0f, B.T0, W));
     float hbar_scale = 1.0f;   // 1/sqrt2 when T0 came through the skip input
     for (int l = nh - 1; l >= 0; --l) {
@@ -559,7 +594,7 @@ static int network_backward(tsdfs_field *F, const float *o, const float *v, cons
             Zb[r * W + j] = hsc * Hb[r * W + j] * sig(beta * Z[r * W + j]) + Z2[r * W + j];
         });
         BLAS(gemm_rm(G, true, false, out, in, R, 1.0f, B.T1, W, B.X[l], in, 1.0f, gW(l), in));
-        BLAS(colsum(h, R, out, B.T1, W, B.ones, gb(l)));
+        BLAS(colsum(st, R, out, B.T1, W, B.part, gb(l)));
         if (l > 0) {
             BLAS(gemm_rm(G, false, false, R, in, out, 1.0f, B.T1, W, Wl(l), in, 0.0f, B.T0, W));
             hbar_scale = (l == skip) ? rs2 : 1.0f;
