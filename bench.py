@@ -67,6 +67,20 @@ def field_flops_per_sample(sdf, col):
     return 2 * (fwd + rev + colour), 2 * fwd
 
 
+def train_flops_per_row(sdf, col):
+    """Algorithmic FLOP per row (sample or eikonal point) of the training
+    backward as implemented: the forward recomputed (hidden F_h + output
+    W n_y), the reverse pass for d f / d x (F_h), the colour forward and its
+    backward (3 C), the adjoint of the reverse pass (2 F_h) and first-order
+    backprop (2 F_h + 2 W n_y less the first layer's input gradient):
+    6 F_h + 3 W n_y + 3 C - d_gamma d_out0 multiply-adds."""
+    dims = sdf.layer_dims()
+    f_h = sum(i * o for i, o in dims[:-1])
+    w_ny = dims[-1][0] * dims[-1][1]
+    c = sum(i * o for i, o in col.layer_dims())
+    return 2 * (6 * f_h + 3 * w_ny + 3 * c - dims[0][0] * dims[0][1])
+
+
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
@@ -455,9 +469,14 @@ def main():
             end.record()
             torch.cuda.synchronize()
             tms = start.elapsed_time(end) / n_t
+            S_t = int(out_t[4])
+            t_flop = S_t * fl_sample + (S_t + 8192) * train_flops_per_row(cfg.sdf, cfg.color)
+            t_peak = PEAK_TFLOPS["f32" if tprec == _lib.FP32 else "bf16"]
             result[tname] = {
-                "rays": 8192, "eikonal_points": 8192, "samples": int(out_t[4]), "ms_per_step": tms,
+                "rays": 8192, "eikonal_points": 8192, "samples": S_t, "ms_per_step": tms,
                 "rays_per_s": 8192 / (tms * 1e-3),
+                "flop_per_step": t_flop, "tflop_per_s": t_flop / (tms * 1e-3) / 1e12,
+                "mfma_frac": t_flop / (tms * 1e-3) / 1e12 / t_peak,
                 "loss_rgb": float(out_t[0].item()), "loss_eik": float(out_t[1].item()),
                 "precision": "f32 (forward and backward)" if tprec == _lib.FP32 else
                              "bf16 product inputs, f32 accumulation (forward and backward)",
