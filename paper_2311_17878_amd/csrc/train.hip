@@ -53,11 +53,74 @@ struct Gemm {
     bool bf16;
     __bf16 *sa, *sb;    // BF16 copies of the two inputs
     size_t cap;         // elements per copy
+    float *part;        // split-K partial products
+    size_t part_cap;    // floats in part
 };
+
+// Weight gradients C[M,N] += A^T B reduce over all R rows (K = R ~ 1e5)
+// into a small output; one product call spreads that over a few
+// workgroups.  Split-K: one partial product per chunk of kSplitRows rows
+// (a strided batched product), then the partials added into C in chunk
+// order, so the result does not depend on scheduling.
+constexpr int kSplitRows = 2048;
+
+static int splitk_chunks(int K) { return (K + kSplitRows - 1) / kSplitRows; }
+
+__global__ void k_splitk_reduce(const float *__restrict__ part, int nb, int M, int N,
+                                float *__restrict__ C, int ldc) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    const int64_t mn = (int64_t)M * N;
+    if (i >= mn) return;
+    float s = 0.0f;
+    for (int b = 0; b < nb; ++b) s += part[b * mn + i];
+    const int r = (int)(i / N), c = (int)(i - (int64_t)r * N);
+    C[(int64_t)r * ldc + c] += s;
+}
 
 // dst[i] = bf16(src[i]) (round to nearest even), n elements
 static void to_bf16_dev(hipStream_t st, const float *src, __bf16 *dst, int64_t n) {
     map(n, st, [=] __device__(int64_t i) { dst[i] = (__bf16)src[i]; });
+}
+
+// Row-major C[M,N] += A^T B with A [K,M] (lda), B [K,N] (ldb), split over K.
+static rocblas_status gemm_splitk(const Gemm &g, int M, int N, int K, const float *A, int lda,
+                                  const float *B, int ldb, float *C, int ldc) {
+    const int nfull = K / kSplitRows, rem = K - nfull * kSplitRows;
+    const int nb = nfull + (rem > 0 ? 1 : 0);
+    const float one = 1.0f, zero = 0.0f;
+    const rocblas_stride sA = (rocblas_stride)kSplitRows * lda;
+    const rocblas_stride sB = (rocblas_stride)kSplitRows * ldb;
+    const rocblas_stride sC = (rocblas_stride)M * N;
+    const rocblas_operation on = rocblas_operation_none, ot = rocblas_operation_transpose;
+    rocblas_status st = rocblas_status_success;
+    // column-major view: part_b^T [N,M] = B_b^T [N,k] (B_b as stored) x A_b [k,M]
+    if (!g.bf16) {
+        if (nfull > 0)
+            st = rocblas_sgemm_strided_batched(g.h, on, ot, N, M, kSplitRows, &one, B, ldb, sB, A,
+                                               lda, sA, &zero, g.part, N, sC, nfull);
+        if (st == rocblas_status_success && rem > 0)
+            st = rocblas_sgemm(g.h, on, ot, N, M, rem, &one, B + nfull * sB, ldb, A + nfull * sA,
+                               lda, &zero, g.part + nfull * sC, N);
+    } else {
+        const size_t na = (size_t)K * lda, nbb = (size_t)K * ldb;
+        if (na > g.cap || nbb > g.cap) return rocblas_status_invalid_size;
+        to_bf16_dev(g.st, A, g.sa, (int64_t)na);
+        to_bf16_dev(g.st, B, g.sb, (int64_t)nbb);
+        const rocblas_datatype bf = rocblas_datatype_bf16_r, f32 = rocblas_datatype_f32_r;
+        if (nfull > 0)
+            st = rocblas_gemm_strided_batched_ex(g.h, on, ot, N, M, kSplitRows, &one, g.sb, bf, ldb,
+                                                 sB, g.sa, bf, lda, sA, &zero, g.part, f32, N, sC,
+                                                 g.part, f32, N, sC, nfull, f32,
+                                                 rocblas_gemm_algo_standard, 0, 0);
+        if (st == rocblas_status_success && rem > 0)
+            st = rocblas_gemm_ex(g.h, on, ot, N, M, rem, &one, g.sb + nfull * sB, bf, ldb,
+                                 g.sa + nfull * sA, bf, lda, &zero, g.part + nfull * sC, f32, N,
+                                 g.part + nfull * sC, f32, N, f32, rocblas_gemm_algo_standard, 0, 0);
+    }
+    if (st != rocblas_status_success) return st;
+    hipLaunchKernelGGL(k_splitk_reduce, dim3((unsigned)((sC + 255) / 256)), dim3(256), 0, g.st,
+                       g.part, nb, M, N, C, ldc);
+    return hipGetLastError() == hipSuccess ? rocblas_status_success : rocblas_status_internal_error;
 }
 
 // Row-major C[M,N] = alpha op(A) op(B) + beta C (op(A): [M,K], op(B): [K,N]).
@@ -65,6 +128,9 @@ static rocblas_status gemm_rm(const Gemm &g, bool ta, bool tb, int M, int N, int
                               const float *A, int lda, const float *B, int ldb, float beta, float *C,
                               int ldc) {
     if (M == 0 || N == 0) return rocblas_status_success;
+    if (ta && !tb && alpha == 1.0f && beta == 1.0f && g.part && K >= 4 * kSplitRows &&
+        (size_t)splitk_chunks(K) * M * N <= g.part_cap)
+        return gemm_splitk(g, M, N, K, A, lda, B, ldb, C, ldc);
     const rocblas_operation oa = ta ? rocblas_operation_transpose : rocblas_operation_none;
     const rocblas_operation ob = tb ? rocblas_operation_transpose : rocblas_operation_none;
     if (!g.bf16)
@@ -221,6 +287,8 @@ struct BwdBufs {
     float *T0, *T1, *T2, *T3;             // scratch [R, max(cin, W+1)]
     float *Z2[kMaxHidden];                 // second-order contributions
     float *part;                           // column-sum partials [ceil(R/1024)][wide]
+    float *splitk;                         // split-K partials [ceil(R/2048)][wide][wide]
+    size_t splitk_cap;
     float *loss;                           // [2] eikonal loss (device)
     __bf16 *ca, *cb;                       // BF16 copies of product inputs [bf16_cap]
     size_t bf16_cap;
@@ -270,6 +338,8 @@ static size_t carve(BwdBufs &b, const tsdfs_field *F, int R, char *base) {
     b.T2 = take((size_t)R * wide);
     b.T3 = take((size_t)R * wide);
     b.part = take((size_t)colsum_chunks(R) * wide);
+    b.splitk_cap = (size_t)splitk_chunks(R) * wide * wide;
+    b.splitk = take(b.splitk_cap);
     b.loss = take(2);
     // every product input is an [R or <= 272 rows][<= 272] row-major block
     b.bf16_cap = (size_t)(R > kMaxRows ? R : kMaxRows) * (kMaxRows + 8);
@@ -308,7 +378,7 @@ static int network_backward(tsdfs_field *F, const float *o, const float *v, cons
     carve(B, F, R, ws);
     B.S = (int)S;
     B.P = (int)P;
-    const Gemm G{h, st, bf16, B.ca, B.cb, B.bf16_cap};
+    const Gemm G{h, st, bf16, B.ca, B.cb, B.bf16_cap, B.splitk, B.splitk_cap};
     const tsdfs_field_desc &d = F->desc;
     const Plan &PL = F->plan;
     const int W = d.width, nh = d.n_hidden, dg = B.dg, cin = B.cin, nf = d.n_feat;
