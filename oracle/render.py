@@ -22,7 +22,8 @@ its initial (whole-grid) range with the conventional sampler, here the 64+64
 hierarchical baseline; recover_select gives those rays, recover_merge puts
 their new outputs in place.
 
-Opacity from the SDF ("density transformed from SDF", below Eq. 1): the NeuS
+Opacity from the SDF (below Eq. 1 the paper turns the SDF into the density
+of Eq. 1 without fixing the map; taken here): the NeuS
 discrete opacity of a section [t - dt/2, t + dt/2],
 alpha = max((Phi(f_prev) - Phi(f_next)) / Phi(f_prev), 0),  Phi(x) = sigmoid(s x),
 with the section-end SDFs extrapolated from the midpoint along the ray,
