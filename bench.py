@@ -147,6 +147,8 @@ def main():
                     help="fine samples per ray of the coarse + fine leg (0: skip the leg)")
     ap.add_argument("--fill-rounds", type=int, default=2,
                     help="rounds of filling unseen voxels on a copy of the volume (0: skip)")
+    ap.add_argument("--no-rho-sweep", dest="rho_sweep", action="store_false",
+                    help="skip the sampling-density sweep")
     ap.add_argument("--no-two-level", dest="two_level", action="store_false",
                     help="skip the two-level volume leg")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -299,7 +301,7 @@ def main():
     # rho samples per traversed voxel (the default rho is the main step)
     sweep = {}
     rho0 = R.rho
-    for num, den in ((1, 3), (rho0[0], rho0[1]), (5, 8), (5, 7)):
+    for num, den in ((1, 3), (rho0[0], rho0[1]), (5, 8), (5, 7)) if args.rho_sweep else ():
         R.rho = (num, den)
         for _ in range(args.warmup):
             R.render(ro_d, rv_d)
@@ -313,7 +315,8 @@ def main():
         sweep[f"{num}/{den}"] = {"ms_per_step": ms_s, "rays_per_s": n_rays / (ms_s * 1e-3),
                                  "samples_per_ray": int(out_s["s_total"].item()) / n_rays}
     R.rho = rho0
-    result["rho_sweep"] = sweep
+    if sweep:
+        result["rho_sweep"] = sweep
     log(f"rho sweep: {sweep}")
 
     # ---- the other precision on the same step
@@ -664,7 +667,7 @@ def main():
             "speedup_tsdf_vs_hs": hs_ms / ms,
             "speedup_full_vs_hs": hs_ms / full_ms if full_ms else None,
         }
-        for v_ in result["rho_sweep"].values():
+        for v_ in result.get("rho_sweep", {}).values():
             v_["speedup_vs_hs"] = hs_ms / v_["ms_per_step"]
         log(f"hs 64+64: {hs_ms:.2f} ms/step")
 
