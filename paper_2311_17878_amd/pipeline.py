@@ -42,6 +42,7 @@ class TsdfRenderer:
         self.t_far = float(t_far)
         self.precision = precision
         self.state = None
+        self.two_level = None
         self.V = None
         self.flags = None
 
@@ -58,6 +59,16 @@ class TsdfRenderer:
 
     def finalize(self, want_v=True):
         self.V, self.flags = ops.finalize(self.grid, self.state, want_v)
+        return self.V, self.flags
+
+    def fuse_two_level(self, batches, want_v=False, n_updates=None):
+        """Build the volume as the two-level form (bricks of 8^3 voxels,
+        integration sums only where the truncation band reaches) from every
+        (o, v, depth) batch, and finalize it to V and the flags Alg. 1
+        reads.  Keeps the two-level buffers in self.two_level; the dense
+        state is not allocated."""
+        self.two_level = ops.sparse_integrate(self.grid, batches, n_updates)
+        self.V, self.flags = ops.sparse_finalize(self.grid, self.two_level, want_v)
         return self.V, self.flags
 
     def fill_unseen(self, depth_of, max_iter=4, cap=1 << 20):

@@ -164,3 +164,30 @@ def test_two_level_edge_cases():
     import ctypes
     assert lib.tsdf_sparse_pool_bytes(-1, ctypes.byref(ctypes.c_size_t(0))) != 0
     assert lib.tsdf_sparse_alloc(ctypes.byref(grid), None, None, None, 0, None) != 0
+
+
+def test_render_from_two_level_volume_equals_dense():
+    """The renderer fed by the two-level volume renders the small scene's
+    view exactly as from the dense volume (same flags, same kernels)."""
+    from paper_2311_17878_amd import ops
+    from paper_2311_17878_amd.pipeline import TsdfRenderer
+    cfg = get_config("c1")
+    g, s = cfg.grid, cfg.sampling
+    grid = ops.make_grid(g.n, g.lo, g.h, g.d_t, g.d_s, g.nb_radius, g.m_consec)
+    F = ops.Field(cfg.sdf.width, cfg.sdf.n_hidden, cfg.sdf.pe_freqs, cfg.sdf.skip_at,
+                  cfg.sdf.n_feat, cfg.color.n_hidden, cfg.sdf.beta, cfg.in_center,
+                  cfg.in_scale, cfg.sdf_params(), cfg.color_params())
+    o, v, d = cfg.integration_rays()
+    ro, rv = (dev(x) for x in cfg.render_rays())
+    Rd = TsdfRenderer(grid, F, s.rho_num, s.rho_den, s.n_min, s.n_max, cfg.neus_s)
+    Rd.integrate(dev(o), dev(v), dev(d))
+    Rd.finalize()
+    Rt = TsdfRenderer(grid, F, s.rho_num, s.rho_den, s.n_min, s.n_max, cfg.neus_s)
+    half = o.shape[0] // 2           # two batches: every batch is marked before any is added
+    Rt.fuse_two_level([(dev(o[:half]), dev(v[:half]), dev(d[:half])),
+                       (dev(o[half:]), dev(v[half:]), dev(d[half:]))], want_v=True)
+    assert Rt.state is None and Rt.two_level["n_band"] > 0
+    assert torch.equal(Rt.flags, Rd.flags)
+    a, b = Rd.render(ro, rv), Rt.render(ro, rv)
+    for k in ("rgb", "depth", "normal", "acc"):
+        assert torch.equal(a[k], b[k]), k
