@@ -178,7 +178,7 @@ def main():
     g, s = cfg.grid, cfg.sampling
     prec = _lib.BF16 if args.precision == "bf16" else _lib.FP32
     t0 = time.time()
-    o, v, d = cfg.integration_rays()
+    o, v, d = cfg.integration_rays(progress=lambda k, n: log(f"depth maps {k}/{n}"))
     ro, rv = cfg.render_rays()
     log(f"inputs: {o.shape[0]} training rays, {ro.shape[0]} render rays ({time.time() - t0:.1f} s)")
     dev = lambda a: torch.as_tensor(np.ascontiguousarray(a)).cuda()

@@ -79,15 +79,20 @@ class Config:
             self._scene = self.build_scene()
         return self._scene
 
-    def integration_rays(self, views=None):
-        """FP32 (o, v, depth) of the training views (all, or a subset)."""
+    def integration_rays(self, views=None, progress=None):
+        """FP32 (o, v, depth) of the training views (all, or a subset);
+        progress(done, total), if given, is called every 25 depth maps."""
         sc = self.scene()
         vs = self.integ_views(sc)
         if views is not None:
             vs = [vs[i] for i in views]
         workers = max(1, min(16, os.cpu_count() or 1, len(vs)))
+        ds_ = []
         with ThreadPoolExecutor(workers) as ex:
-            ds_ = list(ex.map(lambda ov: ray_depth(sc, ov[0], ov[1]), vs))
+            for k, dk in enumerate(ex.map(lambda ov: ray_depth(sc, ov[0], ov[1]), vs)):
+                ds_.append(dk)
+                if progress is not None and (k + 1) % 25 == 0:
+                    progress(k + 1, len(vs))
         if self.depth_noise is not None:
             ids = range(len(vs)) if views is None else views
             ds_ = [self._noisy(d, i) for d, i in zip(ds_, ids)]
