@@ -147,6 +147,8 @@ def main():
                     help="fine samples per ray of the coarse + fine leg (0: skip the leg)")
     ap.add_argument("--fill-rounds", type=int, default=2,
                     help="rounds of filling unseen voxels on a copy of the volume (0: skip)")
+    ap.add_argument("--no-graph", dest="graph", action="store_false",
+                    help="skip the recorded-graph leg")
     ap.add_argument("--no-rho-sweep", dest="rho_sweep", action="store_false",
                     help="skip the sampling-density sweep")
     ap.add_argument("--no-two-level", dest="two_level", action="store_false",
@@ -296,6 +298,61 @@ def main():
             "paper_context": "1.445e6 rays/s (0.692 us/ray, 39.0 M rays in 27.02 s, GPU unnamed)",
         },
     }
+
+    # ---- the small scene (64^3 volume, 64-wide networks) and its 4096-ray
+    # view: eager renders against replays of one recorded HIP graph, host
+    # wall clock over 100 back-to-back renders each, and the median latency
+    # of single frames (launch, run, wait)
+    if args.graph:
+        cs = get_config("c1")
+        gs_, ss_ = cs.grid, cs.sampling
+        grid_s = ops.make_grid(gs_.n, gs_.lo, gs_.h, gs_.d_t, gs_.d_s, gs_.nb_radius,
+                               gs_.m_consec)
+        field_s = ops.Field(cs.sdf.width, cs.sdf.n_hidden, cs.sdf.pe_freqs, cs.sdf.skip_at,
+                            cs.sdf.n_feat, cs.color.n_hidden, cs.sdf.beta, cs.in_center,
+                            cs.in_scale, cs.sdf_params(), cs.color_params())
+        Rs = TsdfRenderer(grid_s, field_s, ss_.rho_num, ss_.rho_den, ss_.n_min, ss_.n_max,
+                          cs.neus_s, ss_.t_far, prec)
+        so, sv, sd = cs.integration_rays()
+        Rs.integrate(dev(so), dev(sv), dev(sd))
+        Rs.finalize(want_v=False)
+        o_s, v_s = (dev(x) for x in cs.render_rays())
+        for _ in range(5):
+            Rs.render(o_s, v_s)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(100):
+            Rs.render(o_s, v_s)
+        torch.cuda.synchronize()
+        eager_ms = (time.perf_counter() - t0) / 100 * 1e3
+        graph_r, out_g = Rs.capture(o_s, v_s)
+        graph_r.replay()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(100):
+            graph_r.replay()
+        torch.cuda.synchronize()
+        graph_ms = (time.perf_counter() - t0) / 100 * 1e3
+        # latency of one frame: launch, run and wait, one at a time
+        lat = {}
+        for name_, fn_ in (("eager", lambda: Rs.render(o_s, v_s)), ("graph", graph_r.replay)):
+            ts_ = []
+            for _ in range(50):
+                t0 = time.perf_counter()
+                fn_()
+                torch.cuda.synchronize()
+                ts_.append((time.perf_counter() - t0) * 1e3)
+            lat[name_] = float(np.median(ts_))
+        ref_s = Rs.render(o_s, v_s)
+        torch.cuda.synchronize()
+        result["graph"] = {"workload": "c1: 4096-ray view of the 64^3 volume, 64-wide networks",
+                           "eager_ms": eager_ms, "graph_ms": graph_ms,
+                           "speedup": eager_ms / graph_ms,
+                           "frame_latency_ms": lat,
+                           "rays_per_s_graph": 4096 / (graph_ms * 1e-3),
+                           "equal_to_eager": bool(torch.equal(out_g["rgb"], ref_s["rgb"]))}
+        log(f"graph: {result['graph']}")
+        del graph_r, out_g, Rs, field_s
 
     # ---- sampling density swept over the paper's 13-28 samples per ray:
     # rho samples per traversed voxel (the default rho is the main step)

@@ -98,6 +98,20 @@ class TsdfRenderer:
         return sizes
 
     # ---------------------------------------------------------- render ----
+    def capture(self, o, v):
+        """Record one render of the rays in o, v (device tensors whose shapes
+        stay fixed) as a HIP graph.  Returns (graph, out): graph.replay()
+        renders whatever rays o, v hold at replay time into the tensors of
+        out (overwritten by every replay).  The render path has no host
+        synchronisation and no memset; a warm-up render first allocates the
+        workspaces outside the capture."""
+        self.render(o, v)
+        torch.cuda.synchronize()
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph):
+            out = self.render(o, v)
+        return graph, out
+
     def render(self, o, v, sync=False, keep=False, events=None):
         """Render rays o, v [R,3].  `events`: optional dict that receives
         (start, end) torch.cuda.Event pairs per stage, recorded on the
