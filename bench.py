@@ -147,6 +147,9 @@ def main():
                     help="fine samples per ray of the coarse + fine leg (0: skip the leg)")
     ap.add_argument("--fill-rounds", type=int, default=2,
                     help="rounds of filling unseen voxels on a copy of the volume (0: skip)")
+    ap.add_argument("--ray-order", default="row", choices=["row", "tile8"],
+                    help="order of the training rays within each view (integration sums do not "
+                         "depend on it)")
     ap.add_argument("--no-graph", dest="graph", action="store_false",
                     help="skip the recorded-graph leg")
     ap.add_argument("--no-rho-sweep", dest="rho_sweep", action="store_false",
@@ -180,7 +183,8 @@ def main():
     g, s = cfg.grid, cfg.sampling
     prec = _lib.BF16 if args.precision == "bf16" else _lib.FP32
     t0 = time.time()
-    o, v, d = cfg.integration_rays(progress=lambda k, n: log(f"depth maps {k}/{n}"))
+    o, v, d = cfg.integration_rays(progress=lambda k, n: log(f"depth maps {k}/{n}"),
+                                   tile=8 if args.ray_order == "tile8" else 0)
     ro, rv = cfg.render_rays()
     log(f"inputs: {o.shape[0]} training rays, {ro.shape[0]} render rays ({time.time() - t0:.1f} s)")
     dev = lambda a: torch.as_tensor(np.ascontiguousarray(a)).cuda()

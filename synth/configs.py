@@ -79,9 +79,12 @@ class Config:
             self._scene = self.build_scene()
         return self._scene
 
-    def integration_rays(self, views=None, progress=None):
+    def integration_rays(self, views=None, progress=None, tile=0):
         """FP32 (o, v, depth) of the training views (all, or a subset);
-        progress(done, total), if given, is called every 25 depth maps."""
+        progress(done, total), if given, is called every 25 depth maps.
+        tile > 0 lists each square view's rays by tile x tile pixel blocks
+        (blocks row by row, pixels row by row inside a block) instead of
+        row by row: the same rays in another order."""
         sc = self.scene()
         vs = self.integ_views(sc)
         if views is not None:
@@ -96,6 +99,10 @@ class Config:
         if self.depth_noise is not None:
             ids = range(len(vs)) if views is None else views
             ds_ = [self._noisy(d, i) for d, i in zip(ds_, ids)]
+        if tile > 0:
+            perms = [tile_order(o.shape[0], tile) for o, _ in vs]
+            vs = [(o[p], v[p]) for (o, v), p in zip(vs, perms)]
+            ds_ = [d[p] for d, p in zip(ds_, perms)]
         return (np.concatenate([o for o, _ in vs]), np.concatenate([v for _, v in vs]),
                 np.concatenate(ds_))
 
@@ -234,6 +241,18 @@ def _room_views(seed, n, size, width, height, fov_x):
             out.append(pinhole_rays(c, fwd, width, height, fov_x_deg=fov_x))
         return out
     return make
+
+
+def tile_order(n, tile):
+    """Pixel order of a square n-pixel image by tile x tile blocks (blocks
+    row by row, pixels row by row inside a block); identity when the image
+    is not square or its side is not a multiple of tile."""
+    side = int(round(n ** 0.5))
+    if side * side != n or side % tile:
+        return np.arange(n)
+    y, x = np.divmod(np.arange(n), side)
+    key = ((y // tile) * (side // tile) + x // tile) * tile * tile + (y % tile) * tile + x % tile
+    return np.argsort(key, kind="stable")
 
 
 # --------------------------------------------------------------- configs ----
