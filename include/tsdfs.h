@@ -6,8 +6,13 @@
  * Conventions for every call
  *   - Array arguments are DEVICE pointers, allocated and owned by the caller,
  *     contiguous, row-major.  No call allocates device memory except
- *     tsdfs_field_create (weights).  Workspaces are caller-provided; their
- *     sizes are returned by the *_ws_bytes queries.
+ *     tsdfs_field_create (weights) and the first sdf_mlp_bwd on a field (its
+ *     rocBLAS handle, kept until tsdfs_field_destroy).  Workspaces are
+ *     caller-provided; their sizes are returned by the *_ws_bytes queries.
+ *   - Calls that take a `const tsdfs_field *` may run concurrently on one
+ *     field; calls that take a non-const `tsdfs_field *` (sdf_mlp_bwd, which
+ *     binds the field's rocBLAS handle to its stream, tsdfs_field_repack,
+ *     tsdfs_field_destroy) must not overlap any other call on that field.
  *   - `stream` is a hipStream_t (NULL = default stream).  Every call is
  *     asynchronous on that stream unless stated otherwise.
  *   - Return value: TSDFS_OK (0) or a negative error code; a message for the
