@@ -173,10 +173,15 @@ __device__ __forceinline__ void layer_t(const BLayer &L, const __bf16 *act, cons
 #pragma unroll
         for (int j = 0; j < NC; ++j) pre(tt == 0 ? s.t0 : s.t1, s.c0 + j, buf[tt][j]);
     if (sync) __syncthreads();
+    // the epilogue is bound by this wave's VALU issue, while a wave of the
+    // other workgroup in its product phase needs an issue slot only once per
+    // MFMA: give the epilogue the higher issue priority
+    __builtin_amdgcn_s_setprio(1);
 #pragma unroll
     for (int tt = 0; tt < NT; ++tt)
 #pragma unroll
         for (int j = 0; j < NC; ++j) epi(acc[tt][j], tt == 0 ? s.t0 : s.t1, s.c0 + j, buf[tt][j]);
+    __builtin_amdgcn_s_setprio(0);
 }
 
 template <class Pre, class Epi>
