@@ -35,8 +35,8 @@ HBM_PEAK_GBS = 8000.0
 FIELD_SOURCES = {"k_field_fp32": ["field_fp32.hip", "field_common.hpp", "common.hpp", "field.hip"],
                  "k_field_bf16": ["field_bf16.hip", "field_common.hpp", "common.hpp", "field.hip"]}
 TRAFFIC = {
-    "k_field_fp32": {"sha256_16": "6f258e257cf685cb", "fetch_kib": 3.504e+07, "write_kib": 5.785e+07},
-    "k_field_bf16": {"sha256_16": "7bbe089a33eac78e", "fetch_kib": 1.895e+07, "write_kib": 2.103e+07},
+    "k_field_fp32": {"sha256_16": "6f258e257cf685cb", "fetch_kib": 3.220e+07, "write_kib": 5.791e+07},
+    "k_field_bf16": {"sha256_16": "6e535fc961931faf", "fetch_kib": 1.936e+07, "write_kib": 2.104e+07},
 }
 COPY_SCALE = {"fetch": 2.0, "write": 1.0}
 
