@@ -169,8 +169,8 @@ def main():
         print(json.dumps({"copy_mib": args.copy_calibration}))
         return
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU design is "
-              "described in DESIGN.md but not built", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}): the library has no "
+              "multi-GPU path; the figure is the throughput of one GPU", file=sys.stderr)
         sys.exit(2)
 
     import torch
