@@ -381,7 +381,8 @@ int composite(const int32_t *offsets, int64_t n_rays, const float *v, const floa
  * accumulation; elementwise work, bias sums and outputs stay FP32).  The
  * products run in rocBLAS, which may allocate its own small workspace on
  * first use.
- * ws: sdf_mlp_bwd_ws_bytes(n_samples + n_eik). */
+ * ws: sdf_mlp_bwd_ws_bytes(n_samples + n_eik).  n_samples + n_eik must be
+ * below 2^22 (4 194 304); both calls return TSDFS_EINVAL otherwise. */
 int composite_bwd(const int32_t *offsets, int64_t n_rays, const float *v, const float *dt,
                   const float *f, const float *grad_f, const float *rgb, float s,
                   const float *d_out_rgb, float *d_f, float *d_grad_f, float *d_rgb,

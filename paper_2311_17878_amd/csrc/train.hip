@@ -64,6 +64,10 @@ struct Gemm {
 // order, so the result does not depend on scheduling.
 constexpr int kSplitRows = 2048;
 
+// rows (samples + eikonal points) of one backward call: every row-major
+// buffer of up to 512 columns stays indexable with 32-bit integers
+constexpr int64_t kMaxBwdRows = ((int64_t)1 << 31) / 512;
+
 static int splitk_chunks(int K) { return (K + kSplitRows - 1) / kSplitRows; }
 
 __global__ void k_splitk_reduce(const float *__restrict__ part, int nb, int M, int N,
@@ -703,6 +707,8 @@ extern "C" {
 
 int sdf_mlp_bwd_ws_bytes(const tsdfs_field *F, int64_t n_rows, size_t *bytes) {
     TSDFS_CHECK_ARG(F && bytes && n_rows >= 0, "bad arguments");
+    TSDFS_CHECK_ARG(n_rows < kMaxBwdRows, "too many rows (%lld >= %lld)", (long long)n_rows,
+                    (long long)kMaxBwdRows);
     BwdBufs b;
     *bytes = carve(b, F, (int)n_rows, nullptr);
     return TSDFS_OK;
@@ -715,7 +721,7 @@ int sdf_mlp_bwd(tsdfs_field *F, const float *o, const float *v, const float *t,
                 void *ws, size_t ws_bytes, void *stream) {
     TSDFS_CHECK_ARG(F != nullptr, "field is NULL");
     TSDFS_CHECK_ARG(n_samples >= 0 && n_eik >= 0, "negative sizes");
-    TSDFS_CHECK_ARG(n_samples + n_eik < ((int64_t)1 << 31) / 512, "too many rows");
+    TSDFS_CHECK_ARG(n_samples + n_eik < kMaxBwdRows, "too many rows");
     if (precision != TSDFS_FP32 && precision != TSDFS_BF16) {
         set_error("sdf_mlp_bwd: precision %d not supported", precision);
         return TSDFS_EUNSUPPORTED;

@@ -211,3 +211,23 @@ def test_train_step_matches_oracle_and_fd(name, n_rays, n_eik, prec):
             assert rel <= 1e-3
         else:
             assert rel <= 0.1
+
+
+def test_backward_row_limit():
+    """The backward's workspace query and the backward itself accept fewer
+    than 2^22 rows (samples + eikonal points) and reject more with
+    TSDFS_EINVAL, launching nothing."""
+    import ctypes
+    from paper_2311_17878_amd import _lib as L
+    F = make_field(get_config("c1"))
+    lib = L.load()
+    b = ctypes.c_size_t(0)
+    assert lib.sdf_mlp_bwd_ws_bytes(F.handle, (1 << 22) - 1, ctypes.byref(b)) == L.TSDFS_OK
+    assert b.value > 0
+    assert lib.sdf_mlp_bwd_ws_bytes(F.handle, 1 << 22, ctypes.byref(b)) == L.TSDFS_EINVAL
+    assert lib.sdf_mlp_bwd_ws_bytes(F.handle, 1 << 40, ctypes.byref(b)) == L.TSDFS_EINVAL
+    z = torch.zeros(16, device="cuda")
+    p = ctypes.c_void_p(z.data_ptr())
+    rc = lib.sdf_mlp_bwd(F.handle, p, p, p, p, 1 << 21, p, 1 << 21, 0.1, None, None, p, L.FP32,
+                         p, p, None, p, 16, None)
+    assert rc == L.TSDFS_EINVAL
