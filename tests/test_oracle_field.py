@@ -229,3 +229,147 @@ def test_recover_select_and_merge_by_hand():
     assert m["acc"][idx].tolist() == [0.5, 0.6, 0.7, 0.8]
     assert (m["rgb"][idx] == -1).all() and (m["rgb"][[0, 1, 6]] == out["rgb"][[0, 1, 6]]).all()
     assert np.isnan(out["acc"][4])            # the input is untouched
+
+
+# ----------------------------------------------------------------------------
+# Closed-form pins of the network composition (Sec. 3.1, below Eq. 1; the
+# supplementary normal): tiny networks with chosen weights whose outputs
+# follow by hand, so that a swapped concatenation, a missing 1/sqrt(2), a
+# wrong activation or a wrong input order each changes a checked value.
+
+class _Cfg:
+    """The fields of a workload configuration that the oracle field reads."""
+
+    def __init__(self, sdf, color, center, scale):
+        self.sdf, self.color, self.in_center, self.in_scale = sdf, color, center, scale
+
+
+def _sp(z, beta=100.0):
+    return math.log1p(math.exp(-beta * abs(z))) / beta + max(z, 0.0)
+
+
+def _sig(z):
+    return 1.0 / (1.0 + math.exp(-z))
+
+
+def _skip_net():
+    """PE(1) (9-d encoding), two hidden layers, the second one's input the
+    concatenation [h_0, gamma] / sqrt(2); width 10 so layer 0 has 1 unit."""
+    net = SdfNet(width=10, n_hidden=2, pe_freqs=1, skip_at=1, n_feat=2, beta=100.0)
+    assert net.layer_dims() == [(9, 1), (10, 10), (10, 3)]
+    W0 = np.zeros((1, 9)); W0[0, 4] = 2.0          # 2 sin(x_hat_1)
+    b0 = np.array([-0.3125])
+    W1 = np.zeros((10, 10)); b1 = np.zeros(10)
+    W1[0, 0] = 1.0                                  # h_0 / sqrt(2)
+    W1[1, 1] = 1.0                                  # gamma_0 / sqrt(2) = x_hat_0 / sqrt(2)
+    W1[2, 8] = 1.0                                  # gamma_7 / sqrt(2) = cos(x_hat_1) / sqrt(2)
+    W1[3, 6] = -1.0; b1[3] = 0.0625                 # -sin(x_hat_2)/sqrt(2) + 1/16
+    W2 = np.zeros((3, 10)); b2 = np.array([0.125, 0.0, 0.25])
+    W2[0, :4] = [1.0, 2.0, -1.0, 0.5]               # y0
+    W2[1, 1] = 3.0                                  # feat_0
+    W2[2, 4] = 1.0                                  # feat_1 = softplus(0) + 0.25
+    params = np.concatenate([W0.ravel(), b0, W1.ravel(), b1, W2.ravel(), b2]).astype(np.float32)
+    return net, params
+
+
+def _skip_net_by_hand(xh, beta=100.0):
+    x0, x1, x2 = xh
+    z0 = 2.0 * math.sin(x1) - 0.3125
+    h0 = _sp(z0, beta)
+    r = 1.0 / math.sqrt(2.0)
+    z1 = [r * h0, r * x0, r * math.cos(x1), -r * math.sin(x2) + 0.0625]
+    h1 = [_sp(z, beta) for z in z1]
+    y0 = h1[0] + 2.0 * h1[1] - h1[2] + 0.5 * h1[3] + 0.125
+    feat = [3.0 * h1[1], _sp(0.0, beta) + 0.25]
+    # d y0 / d x_hat by the chain rule (softplus_beta' = sigmoid(beta z))
+    s = [_sig(beta * z) for z in z1]
+    g = [2.0 * s[1] * r,
+         s[0] * r * _sig(beta * z0) * 2.0 * math.cos(x1) - s[2] * r * (-math.sin(x1)),
+         0.5 * s[3] * (-r * math.cos(x2))]
+    return y0, feat, g
+
+
+def test_skip_and_encoding_composition_closed_form():
+    net, params = _skip_net()
+    layers = F.as_layers(params, net.layer_dims())
+    center, scale = (0.5, -0.25, 0.125), 2.0
+    xh = np.array([[0.013, 0.161, -0.027], [-0.004, 0.3, 0.2], [0.02, -0.05, 0.9]])
+    p = torch.tensor(np.asarray(center) + scale * xh, dtype=torch.float64, requires_grad=True)
+    f, feat, x_hat = F.sdf_forward(net, layers, p, center, scale)
+    (g,) = torch.autograd.grad(f.sum(), p)
+    for i in range(xh.shape[0]):
+        y0, ft, gg = _skip_net_by_hand(x_hat[i].detach().numpy())
+        assert f[i].item() == pytest.approx(scale * y0, rel=1e-13, abs=1e-15)
+        np.testing.assert_allclose(feat[i].detach().numpy(), ft, rtol=1e-13, atol=1e-15)
+        # grad f with respect to world p: f = scale y0(x_hat), x_hat = (p - c)/scale
+        np.testing.assert_allclose(g[i].numpy(), gg, rtol=1e-11, atol=1e-14)
+
+
+def test_skip_composition_detects_plausible_mistakes():
+    """The closed form above separates the right composition from a swapped
+    concatenation, a missing 1/sqrt(2) and ReLU in place of softplus."""
+    xh = (0.013, 0.161, -0.027)
+    y_ok = _skip_net_by_hand(xh)[0]
+    x0, x1, x2 = xh
+    h0 = _sp(2.0 * math.sin(x1) - 0.3125)
+    gam = [x0, x1, x2, math.sin(x0), math.sin(x1), math.sin(x2), math.cos(x0), math.cos(x1),
+           math.cos(x2)]
+
+    def y(u, act):
+        z = [u[0], u[1], u[8], -u[6] + 0.0625]
+        h = [act(v) for v in z]
+        return h[0] + 2.0 * h[1] - h[2] + 0.5 * h[3] + 0.125
+
+    r = 1.0 / math.sqrt(2.0)
+    variants = {
+        "swapped": y([r * v for v in gam + [h0]], _sp),
+        "no sqrt2": y([h0] + gam, _sp),
+        "relu": y([r * v for v in [max(2.0 * math.sin(x1) - 0.3125, 0.0)] + gam],
+                  lambda v: max(v, 0.0)),
+    }
+    for name, yv in variants.items():
+        assert abs(yv - y_ok) > 1e-4, name
+
+
+def _feature_net():
+    """SDF net with one hidden unit and one feature: y0 = softplus(x_hat_0),
+    feat = 2 y0 + 0.5; grad f = (sigmoid(beta x_hat_0), 0, 0)."""
+    net = SdfNet(width=1, n_hidden=1, pe_freqs=0, skip_at=-1, n_feat=1, beta=100.0)
+    params = np.array([1.0, 0.0, 0.0, 0.0, 1.0, 2.0, 0.0, 0.5], np.float32)
+    return net, params
+
+
+@pytest.mark.parametrize("j", range(10))
+def test_color_input_order_relu_sigmoid_closed_form(j):
+    """Colour network [x_hat, v, grad f, feat] -> ReLU -> sigmoid(3): a
+    hidden layer that selects input j (+ and - copies), through the oracle's
+    whole field evaluation, equals the hand-computed sigmoid of the chosen
+    input's ReLU'd value."""
+    snet, sparams = _feature_net()
+    cnet = ColorNet(width=2, n_hidden=1, n_feat=1)
+    assert cnet.layer_dims() == [(10, 2), (2, 3)]
+    W0 = np.zeros((2, 10)); W0[0, j] = 1.0; W0[1, j] = -1.0
+    b0 = np.zeros(2)
+    W1 = np.array([[1.0, 0.0], [0.0, 1.0], [2.0, -1.0]]); b1 = np.array([0.125, -0.1875, 0.0])
+    cparams = np.concatenate([W0.ravel(), b0, W1.ravel(), b1]).astype(np.float32)
+    center, scale = (0.25, 0.5, -0.5), 1.5
+    cfg = _Cfg(snet, cnet, center, scale)
+    sl = F.as_layers(sparams, snet.layer_dims())
+    cl = F.as_layers(cparams, cnet.layer_dims())
+    xh = np.array([0.004, -0.3, 0.45])
+    v = np.array([0.48, -0.6, 0.64])
+    p = torch.tensor([np.asarray(center) + scale * xh], dtype=torch.float64)
+    f, g, rgb = F.field(cfg, sl, cl, p, torch.tensor([v], dtype=torch.float64))
+    h = _sp(xh[0])
+    grad = [_sig(100.0 * xh[0]), 0.0, 0.0]
+    assert f[0].item() == pytest.approx(scale * h, rel=1e-13)
+    np.testing.assert_allclose(g[0].numpy(), grad, rtol=1e-13, atol=1e-16)
+    inputs = list(xh) + list(v) + grad + [2.0 * h + 0.5]
+    a = inputs[j]
+    hid = (max(a, 0.0), max(-a, 0.0))
+    exp = [_sig(hid[0] + 0.125), _sig(hid[1] - 0.1875), _sig(2.0 * hid[0] - hid[1])]
+    np.testing.assert_allclose(rgb[0].numpy(), exp, rtol=1e-13, atol=1e-16)
+    # every other input order gives a different value for this j
+    others = [k for k in range(10) if inputs[k] != a]
+    assert others and all(abs(_sig(max(inputs[k], 0) + 0.125) - exp[0]) > 1e-6 or
+                          abs(_sig(max(-inputs[k], 0) - 0.1875) - exp[1]) > 1e-6 for k in others)

@@ -374,3 +374,62 @@ def test_frontier_fill_covers_free_space_small_scene():
     assert not (~seen & (cl > 0)).any()
     assert not (seen & (cl < -(g.d_t + np.sqrt(3.0) * g.h))).any()
     assert (~seen & (cl < -(g.d_t + np.sqrt(3.0) * g.h))).sum() > 1000   # interiors stay unseen
+
+
+def slab_range(grid, o, v):
+    """[t_in, t_out] of the snapped ray inside the grid box by the slab test
+    on exact rationals, t_in clipped at 0; None when the interval is empty."""
+    O, V = snapped(o, v)
+    LO = [int(round(x * Q)) for x in grid.lo]
+    H = int(round(grid.h * Q))
+    t0, t1 = Fr(0), None
+    for a in range(3):
+        b0, b1 = LO[a], LO[a] + grid.n[a] * H
+        if V[a] == 0:
+            if not b0 <= O[a] < b1:
+                return None
+            continue
+        lo_t, hi_t = sorted((Fr(b0 - O[a], V[a]), Fr(b1 - O[a], V[a])))
+        t0 = max(t0, lo_t)
+        t1 = hi_t if t1 is None else min(t1, hi_t)
+    return (t0, t1) if t1 is not None and t1 > t0 else None
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_ray_range_is_the_slab_interval(seed):
+    """The oracle's grid range equals the exact slab interval of the snapped
+    ray rounded once to FP32 (0, 0 when the ray misses the box)."""
+    rng = np.random.default_rng(100 + seed)
+    grid = Grid((8, 6, 5), (-0.5, -0.375, -0.25), 1.0 / 8, 3.0 / 8, 1.0 / 8)
+    R = 64
+    o = rng.normal(size=(R, 3)) * (0.3 if seed % 2 else 1.5)
+    v = rng.normal(size=(R, 3))
+    v /= np.linalg.norm(v, axis=1, keepdims=True)
+    o, v = o.astype(np.float32), v.astype(np.float32)
+    t_in, t_out = tsdf.ray_range(grid, o, v)
+    hits = 0
+    for r in range(R):
+        e = slab_range(grid, o[r], v[r])
+        if e is None:
+            assert t_in[r] == 0 and t_out[r] == 0
+        else:
+            hits += 1
+            assert t_in[r] == f32(e[0]) and t_out[r] == f32(e[1])
+    assert hits > 0
+
+
+def test_ray_range_by_hand():
+    grid = Grid((4, 4, 4), (0.0, 0.0, 0.0), 0.25, 0.75, 0.25)
+    o = np.array([[-1.0, 0.375, 0.625],    # from outside along +x: [1, 2]
+                  [0.5, 0.5, 0.5],          # from inside along +z: [0, 0.5]
+                  [2.0, 2.0, 2.0],          # misses
+                  [2.0, 0.5, 0.5],          # box behind the camera
+                  [-1.0, -1.0, 0.5]],       # diagonal in the xy plane: [sqrt2, 2 sqrt2]
+                 np.float32)
+    s = np.float32(np.sqrt(0.5))
+    v = np.array([[1, 0, 0], [0, 0, 1], [1, 0, 0], [1, 0, 0], [s, s, 0]], np.float32)
+    t_in, t_out = tsdf.ray_range(grid, o, v)
+    assert list(t_in[:4]) == [1.0, 0.0, 0.0, 0.0] and list(t_out[:4]) == [2.0, 0.5, 0.0, 0.0]
+    # the snapped diagonal direction is rne(2^20 sqrt(1/2)) per axis
+    Vq = np.rint(np.float64(s) * Q)
+    assert t_in[4] == np.float32(Q / Vq) and t_out[4] == np.float32(2 * Q / Vq)
