@@ -6,13 +6,13 @@
  * Conventions for every call
  *   - Array arguments are DEVICE pointers, allocated and owned by the caller,
  *     contiguous, row-major.  No call allocates device memory except
- *     tsdfs_field_create (weights) and the first sdf_mlp_bwd on a field (its
- *     rocBLAS handle, kept until tsdfs_field_destroy).  Workspaces are
- *     caller-provided; their sizes are returned by the *_ws_bytes queries.
+ *     tsdfs_field_create (weights, freed by tsdfs_field_destroy).  Workspaces
+ *     are caller-provided; their sizes are returned by the *_ws_bytes queries.
  *   - Calls that take a `const tsdfs_field *` may run concurrently on one
- *     field; calls that take a non-const `tsdfs_field *` (sdf_mlp_bwd, which
- *     binds the field's rocBLAS handle to its stream, tsdfs_field_repack,
- *     tsdfs_field_destroy) must not overlap any other call on that field.
+ *     field (each with its own workspace); calls that take a non-const
+ *     `tsdfs_field *` (tsdfs_field_repack, tsdfs_field_destroy, and the
+ *     parameter updates made through tsdfs_field_params) must not overlap
+ *     any other call on that field.
  *   - `stream` is a hipStream_t (NULL = default stream).  Every call is
  *     asynchronous on that stream unless stated otherwise.
  *   - Return value: TSDFS_OK (0) or a negative error code; a message for the
@@ -360,12 +360,20 @@ int composite(const int32_t *offsets, int64_t n_rays, const float *v, const floa
  * Training backward (the paper envisions moving the TSDF bounds into training,
  * Sec. 5 "Limitations and Future Work"; this is one step of it).
  *
- * composite_bwd: adjoint of composite() for the rgb output: given d_out_rgb
- * [n_rays,3], writes per-sample d_f [S], d_grad_f [S,3] (through the NeuS
- * opacity's cos = min(v.grad f, 0)) and d_rgb [S,3].  Inputs as in composite().
+ * composite_bwd: adjoint of composite() (Eq. 1 colour, Eq. 2 depth, the
+ * supplementary normal, and the weight sum acc).  Given the per-ray
+ * adjoints d_out_rgb [n_rays,3], d_out_depth [n_rays], d_out_normal
+ * [n_rays,3] and d_out_acc [n_rays] (each may be NULL: zero), writes the
+ * per-sample d_f [S], d_grad_f [S,3] (through the NeuS opacity's
+ * cos = min(v.grad f, 0) and through the normalised normal grad f/|grad f|)
+ * and d_rgb [S,3].  Depth and normal are normalised by acc, so their
+ * adjoints are zero for rays with acc = 0 (where both outputs are 0).  The
+ * sample positions t are inputs, not differentiated.  Inputs as in
+ * composite(); one thread per ray, deterministic.
  *
- * rgb_loss: loss = (1/B) sum_rays |rgb - target|^2 (device scalar, reset by
- * the call), d_rgb = 2 (rgb - target) / B.
+ * rgb_loss: loss = (1/B) sum_rays |rgb - target|^2 (device scalar, written
+ * by the call; summed by one workgroup in a fixed order, so its bits do not
+ * vary from run to run), d_rgb = 2 (rgb - target) / B.
  *
  * sdf_mlp_bwd: weight gradients of
  *   sum_i (d_f_i f_i + d_grad_f_i . grad f_i + d_rgb_i . rgb_i)
@@ -378,19 +386,22 @@ int composite(const int32_t *offsets, int64_t n_rays, const float *v, const floa
  * sdf_mlp_fwd).  d_f, d_grad_f may be NULL (zero).  eik_loss (optional,
  * device float) receives the eikonal term.  precision: TSDFS_FP32, or
  * TSDFS_BF16 (every matrix product takes BF16-rounded inputs with FP32
- * accumulation; elementwise work, bias sums and outputs stay FP32).  The
- * products run in rocBLAS, which may allocate its own small workspace on
- * first use.
- * ws: sdf_mlp_bwd_ws_bytes(n_samples + n_eik).  n_samples + n_eik must be
- * below 2^22 (4 194 304); both calls return TSDFS_EINVAL otherwise. */
-int composite_bwd(const int32_t *offsets, int64_t n_rays, const float *v, const float *dt,
-                  const float *f, const float *grad_f, const float *rgb, float s,
-                  const float *d_out_rgb, float *d_f, float *d_grad_f, float *d_rgb,
+ * accumulation; elementwise work, bias sums and outputs stay FP32).  Every
+ * product runs in the library's own MFMA kernels; the weight gradients and
+ * the bias and loss sums reduce over the rows in a fixed order, so repeated
+ * calls give identical bits.  No allocation.
+ * ws: sdf_mlp_bwd_ws_bytes(n_samples + n_eik) bytes, 256-byte aligned.
+ * n_samples + n_eik must be below 2^22 (4 194 304); both calls return
+ * TSDFS_EINVAL otherwise. */
+int composite_bwd(const int32_t *offsets, int64_t n_rays, const float *v, const float *t,
+                  const float *dt, const float *f, const float *grad_f, const float *rgb, float s,
+                  const float *d_out_rgb, const float *d_out_depth, const float *d_out_normal,
+                  const float *d_out_acc, float *d_f, float *d_grad_f, float *d_rgb,
                   void *stream);
 int rgb_loss(const float *rgb, const float *target, int64_t n_rays, float *d_rgb, float *loss,
              void *stream);
 int sdf_mlp_bwd_ws_bytes(const tsdfs_field *field, int64_t n_rows, size_t *bytes);
-int sdf_mlp_bwd(tsdfs_field *field, const float *o, const float *v, const float *t,
+int sdf_mlp_bwd(const tsdfs_field *field, const float *o, const float *v, const float *t,
                 const int32_t *ray_id, int64_t n_samples, const float *eik_x, int64_t n_eik,
                 float eik_lambda, const float *d_f, const float *d_grad_f, const float *d_rgb,
                 int32_t precision, float *d_params_sdf, float *d_params_color, float *eik_loss,

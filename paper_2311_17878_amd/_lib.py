@@ -77,7 +77,7 @@ SIGNATURES = {
     "sdf_mlp_fwd_ws_bytes": [P, P],
     "sdf_mlp_fwd": [P, P, P, P, P, c_int64, P, c_int32, P, P, P, P, c_size_t, P],
     "composite": [P, c_int64, P, P, P, P, P, P, c_float, P, P, P, P, P, P],
-    "composite_bwd": [P, c_int64, P, P, P, P, P, c_float, P, P, P, P, P],
+    "composite_bwd": [P, c_int64, P, P, P, P, P, P, c_float, P, P, P, P, P, P, P, P],
     "rgb_loss": [P, P, c_int64, P, P, P],
     "sdf_mlp_bwd_ws_bytes": [P, c_int64, P],
     "sdf_mlp_bwd": [P, P, P, P, P, c_int64, P, c_int64, c_float, P, P, P, c_int32, P, P, P, P,

@@ -42,19 +42,22 @@ class FieldFn(torch.autograd.Function):
 
 
 class CompositeFn(torch.autograd.Function):
-    """Per-ray colour of Eq. 1 as a function of the samples' f, grad f, rgb."""
+    """Per-ray colour (Eq. 1), depth (Eq. 2), normal and weight sum as
+    functions of the samples' f, grad f and rgb."""
 
     @staticmethod
     def forward(ctx, f, g, rgb, offsets, v, t, dt, s):
         out = ops.composite(offsets, v, t, dt, f, g, rgb, s)
-        ctx.save_for_backward(f, g, rgb, offsets, v, dt)
+        ctx.save_for_backward(f, g, rgb, offsets, v, t, dt)
         ctx.s = s
-        return out["rgb"]
+        return out["rgb"], out["depth"], out["normal"], out["acc"]
 
     @staticmethod
-    def backward(ctx, d_out):
-        f, g, rgb, offsets, v, dt = ctx.saved_tensors
-        d_f, d_g, d_c = ops.composite_bwd(offsets, v, dt, f, g, rgb, ctx.s, d_out.contiguous())
+    def backward(ctx, d_rgb, d_depth, d_normal, d_acc):
+        f, g, rgb, offsets, v, t, dt = ctx.saved_tensors
+        c = lambda x: None if x is None else x.contiguous()
+        d_f, d_g, d_c = ops.composite_bwd(offsets, v, t, dt, f, g, rgb, ctx.s, c(d_rgb), c(d_depth),
+                                          c(d_normal), c(d_acc))
         return d_f, d_g, d_c, None, None, None, None, None
 
 
@@ -71,7 +74,7 @@ def train_step(renderer, o, v, target, eik_x, eik_lambda=0.1, precision=FP32):
     f, g, rgb = R.field.forward(o, v, p["t"], p["ray_id"], precision=precision)
     out = ops.composite(p["offsets"], v, p["t"], p["dt"], f, g, rgb, R.s)
     loss, d_out = ops.rgb_loss(out["rgb"], target)
-    d_f, d_g, d_c = ops.composite_bwd(p["offsets"], v, p["dt"], f, g, rgb, R.s, d_out)
+    d_f, d_g, d_c = ops.composite_bwd(p["offsets"], v, p["t"], p["dt"], f, g, rgb, R.s, d_out)
     d_sdf, d_col, eik = R.field.backward(o, v, p["t"], p["ray_id"], d_f, d_g, d_c,
                                          eik_x=eik_x, eik_lambda=eik_lambda, precision=precision)
     return loss, eik, d_sdf, d_col, p["S"]

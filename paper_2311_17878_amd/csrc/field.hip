@@ -305,7 +305,6 @@ int tsdfs_field_create(const tsdfs_field_desc *d, const float *sdf_params,
 
 int tsdfs_field_destroy(tsdfs_field *F) {
     if (!F) return TSDFS_OK;
-    release_blas(F);
     if (F->dev) (void)hipFree(F->dev);
     if (F->params_sdf) (void)hipFree(F->params_sdf);
     if (F->plan_f) (void)hipFree(F->plan_f);

@@ -77,7 +77,6 @@ struct NetPlan {
 typedef NetPlan<Layer> Plan;
 typedef NetPlan<BLayer> BPlan;
 
-void release_blas(tsdfs_field *F);
 int repack(const tsdfs_field *F, hipStream_t stream);
 
 int launch_field_bf16(const BPlan &P, int grid, const float *o, const float *v, const float *t,
@@ -107,7 +106,6 @@ struct tsdfs_field {
     size_t w_off[tsdfs::kMaxHidden + 1], b_off[tsdfs::kMaxHidden + 1];
     int cdin[tsdfs::kMaxColor + 1], cdout[tsdfs::kMaxColor + 1];
     size_t cw_off[tsdfs::kMaxColor + 1], cb_off[tsdfs::kMaxColor + 1];
-    void *blas = nullptr;        // rocblas_handle, created on first backward
 };
 
 namespace tsdfs {

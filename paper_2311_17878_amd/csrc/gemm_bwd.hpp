@@ -1,0 +1,263 @@
+// Matrix products of the training backward on the MFMA units (FP32:
+// v_mfma_f32_32x32x2_f32; BF16 inputs: v_mfma_f32_32x32x16_bf16, both with
+// FP32 accumulation), with the elementwise step that follows a product run
+// in its epilogue.
+//
+// Two shapes occur.  Row products C[R, N] = A[R, K] op(W) run over the
+// ~10^5 rows (samples and eikonal points) of a step against one weight
+// matrix (op(W) = W^T for W [N][K], or W for W [K][N]); weight gradients
+// C[M, N] += A[R, M]^T B[R, N] reduce over those rows into a small matrix
+// and are split into chunks of rows (one partial product each, then the
+// partials added in chunk order: deterministic).
+//
+// A workgroup of 4 waves computes a 128 x (32 NB) tile, K in steps of BK:
+// both operands go through LDS as [row][k] tiles (k contiguous, padded row
+// stride, 16-byte aligned rows), so every lane reads its MFMA operand as one
+// 16-byte LDS load.  In FP32 the 8 k of a group are taken as k = 4 h + s in
+// step s by the lanes of half h = lane / 32 (A and B alike, so each product
+// sums over all 8).  BF16 operands are rounded (nearest even) when they are
+// written to LDS, so no converted copy of an input exists in HBM.  Global
+// loads of the next K step are issued before the MFMAs of the current one.
+#pragma once
+
+#include "field_common.hpp"
+
+namespace tsdfs {
+namespace bwd {
+
+constexpr int kBM = 128;
+constexpr int kThreads = 256;
+
+template <bool BF> struct Prec;
+template <> struct Prec<false> {
+    static constexpr int BK = 32, LS = 36, V = 4;   // k per tile, LDS row stride, k per store
+    typedef float T;
+};
+template <> struct Prec<true> {
+    static constexpr int BK = 64, LS = 72, V = 8;
+    typedef __bf16 T;
+};
+
+// An operand as a function of (i, k): i indexes output rows (A) or output
+// columns (B), k the reduction.  kcont: element at p[i ld + k], else
+// p[k ld + i].  Elements with i >= n_i or k >= n_k read as zero.
+struct Opnd {
+    const float *p;
+    int ld, n_i, n_k;
+};
+
+enum { LD_KVEC = 0, LD_KSCALAR = 1, LD_ICONT = 2 };
+
+// Global -> registers -> LDS for one NI x BK tile, V consecutive k per item
+// (one 16-byte LDS store), NI * BK / V / 256 items per thread.  Loads are
+// issued without branches: an element outside the operand reads the
+// operand's first element instead and is zeroed when the registers are
+// written to LDS, so the loads of a step stay in flight together until the
+// store (the entries of an item that are valid form a prefix in k).
+template <bool BF, int NI, int MODE>
+struct Loader {
+    typedef Prec<BF> P;
+    static constexpr int ITEMS = NI * (P::BK / P::V) / kThreads;
+    float r[ITEMS][P::V];
+    int nv[ITEMS];   // valid entries of each item
+
+    __device__ __forceinline__ static void coords(int it, int &row, int &kv) {
+        if (MODE == LD_ICONT) {   // lanes along i: coalesced loads of p[k ld + i]
+            row = it % NI;
+            kv = (it / NI) * P::V;
+        } else {                  // lanes along k within a row
+            row = it / (P::BK / P::V);
+            kv = (it % (P::BK / P::V)) * P::V;
+        }
+    }
+
+    __device__ __forceinline__ void load(const Opnd &o, int i0, int k0, int tid) {
+#pragma unroll
+        for (int q = 0; q < ITEMS; ++q) {
+            int row, kv;
+            coords(tid + kThreads * q, row, kv);
+            const int i = i0 + row, k = k0 + kv;
+            int n = o.n_k - k;
+            n = n < 0 ? 0 : n > P::V ? P::V : n;
+            if (i >= o.n_i) n = 0;
+            nv[q] = n;
+            if (MODE == LD_KVEC) {
+                // 16-byte loads: ld is a multiple of 4 and >= n_k rounded up
+                // to 4, so a load that starts below n_k stays in its row
+#pragma unroll
+                for (int u = 0; u < P::V; u += 4) {
+                    const unsigned off = u < n ? (unsigned)(i * o.ld + k + u) : 0u;
+                    const float4 x = *(const float4 *)(o.p + off);
+                    r[q][u] = x.x;
+                    r[q][u + 1] = x.y;
+                    r[q][u + 2] = x.z;
+                    r[q][u + 3] = x.w;
+                }
+            } else {
+#pragma unroll
+                for (int u = 0; u < P::V; ++u) {
+                    const unsigned off =
+                        u < n ? (unsigned)(MODE == LD_ICONT ? (k + u) * o.ld + i : i * o.ld + k + u)
+                              : 0u;
+                    r[q][u] = o.p[off];
+                }
+            }
+        }
+    }
+
+    // Sum of this thread's masked entries.  In LD_ICONT mode with NI = 128
+    // every item of a thread lies on one row, i = tid % 128, so this is the
+    // thread's share of that row's sum over the step's k (FP32, before any
+    // BF16 rounding).
+    __device__ __forceinline__ float row_sum() const {
+        float s = 0.0f;
+#pragma unroll
+        for (int q = 0; q < ITEMS; ++q)
+#pragma unroll
+            for (int u = 0; u < P::V; ++u) s += u < nv[q] ? r[q][u] : 0.0f;
+        return s;
+    }
+
+    __device__ __forceinline__ void store(typename P::T *lds, int tid) const {
+#pragma unroll
+        for (int q = 0; q < ITEMS; ++q) {
+            int row, kv;
+            coords(tid + kThreads * q, row, kv);
+            float x[P::V];
+#pragma unroll
+            for (int u = 0; u < P::V; ++u) x[u] = u < nv[q] ? r[q][u] : 0.0f;
+            if constexpr (BF) {
+                bf16x8 h;
+#pragma unroll
+                for (int u = 0; u < 8; ++u) h[u] = (__bf16)x[u];   // RNE
+                *(bf16x8 *)(lds + row * P::LS + kv) = h;
+            } else {
+                *(float4 *)(lds + row * P::LS + kv) = make_float4(x[0], x[1], x[2], x[3]);
+            }
+        }
+    }
+};
+
+// Accumulators of one wave: RB x CB blocks of 32 x 32.  Waves are arranged
+// (4 / WC) x WC over the 128 x 32 NB tile.
+template <int RB, int CB>
+struct Acc {
+    floatx16 a[RB][CB];
+};
+
+template <bool BF, int RB, int CB, int WC>
+__device__ __forceinline__ void mma_tile(const typename Prec<BF>::T *As,
+                                         const typename Prec<BF>::T *Bs, Acc<RB, CB> &acc,
+                                         int wave, int lane) {
+    typedef Prec<BF> P;
+    const int wr = wave / WC, wc = wave % WC;
+    const int l32 = lane & 31, h = lane >> 5;
+    if constexpr (!BF) {
+#pragma unroll
+        for (int g = 0; g < P::BK / 8; ++g) {
+            float4 a[RB], b[CB];
+#pragma unroll
+            for (int rb = 0; rb < RB; ++rb)
+                a[rb] = *(const float4 *)(As + ((wr * RB + rb) * 32 + l32) * P::LS + 8 * g + 4 * h);
+#pragma unroll
+            for (int cb = 0; cb < CB; ++cb)
+                b[cb] = *(const float4 *)(Bs + ((wc * CB + cb) * 32 + l32) * P::LS + 8 * g + 4 * h);
+#pragma unroll
+            for (int s = 0; s < 4; ++s)
+#pragma unroll
+                for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+                    for (int cb = 0; cb < CB; ++cb) {
+                        const float av = s == 0 ? a[rb].x : s == 1 ? a[rb].y : s == 2 ? a[rb].z : a[rb].w;
+                        const float bv = s == 0 ? b[cb].x : s == 1 ? b[cb].y : s == 2 ? b[cb].z : b[cb].w;
+                        acc.a[rb][cb] = __builtin_amdgcn_mfma_f32_32x32x2f32(av, bv, acc.a[rb][cb], 0, 0, 0);
+                    }
+        }
+    } else {
+#pragma unroll
+        for (int s = 0; s < P::BK / 16; ++s) {
+            bf16x8 a[RB], b[CB];
+#pragma unroll
+            for (int rb = 0; rb < RB; ++rb)
+                a[rb] = *(const bf16x8 *)(As + ((wr * RB + rb) * 32 + l32) * P::LS + 16 * s + 8 * h);
+#pragma unroll
+            for (int cb = 0; cb < CB; ++cb)
+                b[cb] = *(const bf16x8 *)(Bs + ((wc * CB + cb) * 32 + l32) * P::LS + 16 * s + 8 * h);
+#pragma unroll
+            for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+                for (int cb = 0; cb < CB; ++cb)
+                    acc.a[rb][cb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[rb], b[cb], acc.a[rb][cb], 0, 0, 0);
+        }
+    }
+}
+
+// sum over k in [k_begin, k_end) of A(i0 + ., k) B(j0 + ., k) into acc.
+// With a_sum (A in LD_ICONT mode), *a_sum also receives this thread's share
+// of sum_k A(i0 + tid % 128, k) (FP32; tid and tid + 128 share a row).
+template <bool BF, int RB, int CB, int WC, int AMODE, int BMODE>
+__device__ __forceinline__ void tile_product(const Opnd &A, const Opnd &B, int i0, int j0,
+                                             int k_begin, int k_end, Acc<RB, CB> &acc,
+                                             typename Prec<BF>::T *As, typename Prec<BF>::T *Bs,
+                                             float *a_sum = nullptr) {
+    typedef Prec<BF> P;
+    constexpr int BN = WC * CB * 32;
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+#pragma unroll
+    for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+        for (int cb = 0; cb < CB; ++cb) acc.a[rb][cb] = (floatx16)(0.0f);
+    Loader<BF, kBM, AMODE> la;
+    Loader<BF, BN, BMODE> lb;
+    if (k_begin < k_end) {
+        la.load(A, i0, k_begin, tid);
+        lb.load(B, j0, k_begin, tid);
+    }
+    for (int k0 = k_begin; k0 < k_end; k0 += P::BK) {
+        __syncthreads();            // the previous step's MFMAs are done with LDS
+        la.store(As, tid);
+        lb.store(Bs, tid);
+        if (a_sum) *a_sum += la.row_sum();
+        __syncthreads();
+        if (k0 + P::BK < k_end) {   // next step's loads in flight during the MFMAs
+            la.load(A, i0, k0 + P::BK, tid);
+            lb.load(B, j0, k0 + P::BK, tid);
+        }
+        mma_tile<BF, RB, CB, WC>(As, Bs, acc, wave, lane);
+    }
+}
+
+// Visit every element (row, col, value) of the wave's accumulators inside
+// [0, M) x [0, N); rows i0 + ., columns j0 + .  A 32 x 32 block that lies
+// inside entirely takes a path without per-element tests.
+template <int RB, int CB, int WC, class F>
+__device__ __forceinline__ void for_each(const Acc<RB, CB> &acc, int i0, int j0, int M, int N,
+                                         F &&f) {
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int wr = wave / WC, wc = wave % WC;
+    const int l32 = lane & 31, h = lane >> 5;
+#pragma unroll
+    for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+        for (int cb = 0; cb < CB; ++cb) {
+            const int r0 = i0 + (wr * RB + rb) * 32, c0 = j0 + (wc * CB + cb) * 32;
+            const int col = c0 + l32;
+            if (r0 + 32 <= M && c0 + 32 <= N) {
+#pragma unroll
+                for (int e = 0; e < 16; ++e)
+                    f(r0 + 8 * (e >> 2) + 4 * h + (e & 3), col, acc.a[rb][cb][e]);
+            } else if (col < N) {
+#pragma unroll
+                for (int e = 0; e < 16; ++e) {
+                    const int row = r0 + 8 * (e >> 2) + 4 * h + (e & 3);
+                    if (row < M) f(row, col, acc.a[rb][cb][e]);
+                }
+            }
+            // one block at a time: keeps the epilogue's loads from being
+            // hoisted over all blocks at once (register pressure)
+            __builtin_amdgcn_sched_barrier(0);
+        }
+}
+
+}  // namespace bwd
+}  // namespace tsdfs

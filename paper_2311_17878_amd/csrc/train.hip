@@ -1,20 +1,25 @@
-// Training backward: compositing adjoint, photometric loss, and the
-// hand-derived weight gradients of the SDF + colour networks including the
-// second-order path weights -> grad f -> (colour input, opacity, eikonal).
+// Training backward: the hand-derived weight gradients of the SDF + colour
+// networks, including the second-order path weights -> grad f -> (colour
+// input, opacity, eikonal), and the Adam update of a training loop.
 //
 // The network backward is organised layer by layer over all rows (samples
-// and eikonal points) with the activations recomputed inside the call:
-// plain row-major products go to rocBLAS (FP32, or BF16 inputs with FP32
-// accumulation; the bias sums stay FP32), everything elementwise
-// (softplus and its first two derivatives, the encoding Jacobian, masks,
-// the adjoint bookkeeping) runs in the kernels below.
-#include <rocblas/rocblas.h>
+// and eikonal points) with the activations recomputed inside the call.
+// Every matrix product runs on the MFMA units in the kernels of
+// gemm_bwd.hpp (FP32, or BF16 inputs with FP32 accumulation), and the
+// elementwise step that follows a product (bias, softplus and its first
+// two derivatives, ReLU masks, the sigmoid output, the adjoint bookkeeping)
+// runs in that product's epilogue; the remaining elementwise steps (the
+// encoding and its Jacobian, grad f from the encoding rows, the
+// concatenations) are small kernels.  Weight gradients reduce over the rows
+// in chunks (partials added in chunk order) and the bias and loss sums in
+// fixed-order two-pass reductions, so a call is deterministic.
 #include <math.h>
-#include <vector>
 
-#include "field_common.hpp"
+#include "gemm_bwd.hpp"
 
 namespace tsdfs {
+
+using bwd::Opnd;
 
 template <typename F>
 __global__ void k_map(int64_t n, F f) {
@@ -28,144 +33,361 @@ static void map(int64_t n, hipStream_t s, F f) {
     hipLaunchKernelGGL(k_map<F>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, f);
 }
 
-__device__ __forceinline__ float sig(float x) { return 1.0f / (1.0f + expf(-x)); }
+// f(r, j) over rows r < R and columns j < C (a wave per row, 64 columns per
+// grid step in y), without integer division
+template <typename F>
+__global__ void __launch_bounds__(256) k_map2(int R, int C, F f) {
+    const int j = blockIdx.y * 64 + (threadIdx.x & 63);
+    const int r = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (r < R && j < C) f(r, j);
+}
 
-__device__ __forceinline__ float softplus_b(float z, float beta) {
-    return z > 0.0f ? z + log1pf(expf(-beta * z)) / beta : log1pf(expf(beta * z)) / beta;
+template <typename F>
+static void map2(int R, int C, hipStream_t s, F f) {
+    if (R <= 0 || C <= 0) return;
+    hipLaunchKernelGGL(k_map2<F>, dim3((unsigned)((R + 3) / 4), (unsigned)((C + 63) / 64)),
+                       dim3(256), 0, s, R, C, f);
+}
+
+// The epilogues' versions on the hardware exp2 / log2 / reciprocal (about
+// one ulp each, as in the field kernels): sigmoid(x) = 1 / (1 + 2^(-x log2 e)),
+// softplus_beta(z) = max(z, 0) + log2(1 + 2^(-beta log2 e |z|)) ln2 / beta.
+constexpr float kLog2e = 1.4426950408889634f;
+constexpr float kLn2 = 0.6931471805599453f;
+
+__device__ __forceinline__ float sig_hw(float x) {
+    return __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(-kLog2e * x));
+}
+
+__device__ __forceinline__ float softplus_hw(float z, float beta, float ln2_beta) {
+    const float e = __builtin_amdgcn_exp2f(-kLog2e * beta * fabsf(z));
+    return fmaxf(z, 0.0f) + __builtin_amdgcn_logf(1.0f + e) * ln2_beta;
 }
 
 // d gamma_j / d x_hat_a for the one axis a it depends on.
 __device__ __forceinline__ int gamma_axis(int j) { return j < 3 ? j : ((j - 3) % 6) % 3; }
 
-void release_blas(tsdfs_field *F) {
-    if (F && F->blas) {
-        rocblas_destroy_handle((rocblas_handle)F->blas);
-        F->blas = nullptr;
-    }
-}
-
-// Product context: FP32 (rocBLAS SGEMM) or BF16 inputs with FP32
-// accumulation (each input rounded to BF16 into a scratch copy, then
-// rocBLAS gemm_ex with FP32 compute and output).
-struct Gemm {
-    rocblas_handle h;
-    hipStream_t st;
-    bool bf16;
-    __bf16 *sa, *sb;    // BF16 copies of the two inputs
-    size_t cap;         // elements per copy
-    float *part;        // split-K partial products
-    size_t part_cap;    // floats in part
-};
-
-// Weight gradients C[M,N] += A^T B reduce over all R rows (K = R ~ 1e5)
-// into a small output; one product call spreads that over a few
-// workgroups.  Split-K: one partial product per chunk of kSplitRows rows
-// (a strided batched product), then the partials added into C in chunk
-// order, so the result does not depend on scheduling.
-constexpr int kSplitRows = 2048;
+static int round4(int n) { return (n + 3) / 4 * 4; }
 
 // rows (samples + eikonal points) of one backward call: every row-major
 // buffer of up to 512 columns stays indexable with 32-bit integers
 constexpr int64_t kMaxBwdRows = ((int64_t)1 << 31) / 512;
 
-static int splitk_chunks(int K) { return (K + kSplitRows - 1) / kSplitRows; }
+// ------------------------------------------------------------ epilogues ----
 
-__global__ void k_splitk_reduce(const float *__restrict__ part, int nb, int M, int N,
-                                float *__restrict__ C, int ldc) {
-    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    const int64_t mn = (int64_t)M * N;
-    if (i >= mn) return;
-    float s = 0.0f;
-    for (int b = 0; b < nb; ++b) s += part[b * mn + i];
-    const int r = (int)(i / N), c = (int)(i - (int64_t)r * N);
-    C[(int64_t)r * ldc + c] += s;
-}
+// What a row product does with each output element (row r, column n,
+// accumulated value v).  Pointers and leading dimensions per mode below.
+enum {
+    E_STORE,     // o0 = v
+    E_BIAS,      // o0 = v + bias
+    E_SOFTPLUS,  // z = v + bias: o0 = z, o1 = s0 softplus(z); o2 (if set) = i0[n] sigmoid(beta z)
+    E_REV,       // x = s0 v; n < split: o0 = x, o1 = x sigmoid(beta i0); else o2[n - split] = x
+    E_RELU,      // o0 = max(v + bias, 0)
+    E_RGB,       // c = sigmoid(v + bias): o0 = c, o1 = drgb c (1 - c) for sample rows, else 0
+    E_MASK,      // o0 = i0 > 0 ? v : 0
+    E_SO,        // sp = sigmoid(beta i0): o0 = v sp, o1 = v e beta sp (1 - sp), e = i1 or bias[n]
+    E_FO,        // n < split: o0 = s0 v sigmoid(beta i0) + i1
+    E_GRAD       // o0[3 r + a] = sum over n of axis a of (v + i0) i1 (i0 may be NULL)
+};
 
-// dst[i] = bf16(src[i]) (round to nearest even), n elements; four per
-// thread with 16-byte loads and 8-byte stores when both pointers allow it
-__global__ void __launch_bounds__(256) k_to_bf16_x4(const float4 *__restrict__ src,
-                                                    uint2 *__restrict__ dst, int64_t n4) {
-    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (i >= n4) return;
-    const float4 x = src[i];
-    __bf16 b[4] = {(__bf16)x.x, (__bf16)x.y, (__bf16)x.z, (__bf16)x.w};
-    dst[i] = __builtin_bit_cast(uint2, b);
-}
+struct Epi {
+    int mode = E_STORE;
+    float *o0 = nullptr, *o1 = nullptr, *o2 = nullptr;
+    int ld0 = 0, ld1 = 0, ld2 = 0;
+    const float *i0 = nullptr, *i1 = nullptr, *bias = nullptr;
+    int ldi0 = 0, ldi1 = 0;
+    float beta = 0.0f, s0 = 1.0f;
+    float ln2_beta = 0.0f;   // ln 2 / beta (E_SOFTPLUS)
+    int split = 0, S = 0;
+    const float *drgb = nullptr;
+};
 
-static void to_bf16_dev(hipStream_t st, const float *src, __bf16 *dst, int64_t n) {
-    const bool vec = ((uintptr_t)src % 16 == 0) && ((uintptr_t)dst % 8 == 0);
-    const int64_t n4 = vec ? n / 4 : 0;
-    if (n4 > 0)
-        hipLaunchKernelGGL(k_to_bf16_x4, dim3((unsigned)((n4 + 255) / 256)), dim3(256), 0, st,
-                           (const float4 *)src, (uint2 *)dst, n4);
-    const float *s_tail = src + 4 * n4;
-    __bf16 *d_tail = dst + 4 * n4;
-    if (n - 4 * n4 > 0)
-        map(n - 4 * n4, st, [=] __device__(int64_t i) { d_tail[i] = (__bf16)s_tail[i]; });
-}
-
-// Row-major C[M,N] += A^T B with A [K,M] (lda), B [K,N] (ldb), split over K.
-static rocblas_status gemm_splitk(const Gemm &g, int M, int N, int K, const float *A, int lda,
-                                  const float *B, int ldb, float *C, int ldc) {
-    const int nfull = K / kSplitRows, rem = K - nfull * kSplitRows;
-    const int nb = nfull + (rem > 0 ? 1 : 0);
-    const float one = 1.0f, zero = 0.0f;
-    const rocblas_stride sA = (rocblas_stride)kSplitRows * lda;
-    const rocblas_stride sB = (rocblas_stride)kSplitRows * ldb;
-    const rocblas_stride sC = (rocblas_stride)M * N;
-    const rocblas_operation on = rocblas_operation_none, ot = rocblas_operation_transpose;
-    rocblas_status st = rocblas_status_success;
-    // column-major view: part_b^T [N,M] = B_b^T [N,k] (B_b as stored) x A_b [k,M]
-    if (!g.bf16) {
-        if (nfull > 0)
-            st = rocblas_sgemm_strided_batched(g.h, on, ot, N, M, kSplitRows, &one, B, ldb, sB, A,
-                                               lda, sA, &zero, g.part, N, sC, nfull);
-        if (st == rocblas_status_success && rem > 0)
-            st = rocblas_sgemm(g.h, on, ot, N, M, rem, &one, B + nfull * sB, ldb, A + nfull * sA,
-                               lda, &zero, g.part + nfull * sC, N);
-    } else {
-        const size_t na = (size_t)K * lda, nbb = (size_t)K * ldb;
-        if (na > g.cap || nbb > g.cap) return rocblas_status_invalid_size;
-        to_bf16_dev(g.st, A, g.sa, (int64_t)na);
-        to_bf16_dev(g.st, B, g.sb, (int64_t)nbb);
-        const rocblas_datatype bf = rocblas_datatype_bf16_r, f32 = rocblas_datatype_f32_r;
-        if (nfull > 0)
-            st = rocblas_gemm_strided_batched_ex(g.h, on, ot, N, M, kSplitRows, &one, g.sb, bf, ldb,
-                                                 sB, g.sa, bf, lda, sA, &zero, g.part, f32, N, sC,
-                                                 g.part, f32, N, sC, nfull, f32,
-                                                 rocblas_gemm_algo_standard, 0, 0);
-        if (st == rocblas_status_success && rem > 0)
-            st = rocblas_gemm_ex(g.h, on, ot, N, M, rem, &one, g.sb + nfull * sB, bf, ldb,
-                                 g.sa + nfull * sA, bf, lda, &zero, g.part + nfull * sC, f32, N,
-                                 g.part + nfull * sC, f32, N, f32, rocblas_gemm_algo_standard, 0, 0);
+template <int MODE>
+__device__ __forceinline__ void apply(const Epi &e, int r, int n, float v) {
+    // every row-major buffer indexes with 32 bits (rows * ld < 2^31)
+    const unsigned a0 = (unsigned)(r * e.ld0 + n);
+    if constexpr (MODE == E_STORE) {
+        e.o0[a0] = v;
+    } else if constexpr (MODE == E_BIAS) {
+        e.o0[a0] = v + e.bias[n];
+    } else if constexpr (MODE == E_SOFTPLUS) {
+        const float z = v + e.bias[n];
+        e.o0[a0] = z;
+        e.o1[(unsigned)(r * e.ld1 + n)] = e.s0 * softplus_hw(z, e.beta, e.ln2_beta);
+        if (e.o2) e.o2[(unsigned)(r * e.ld2 + n)] = e.i0[n] * sig_hw(e.beta * z);
+    } else if constexpr (MODE == E_REV) {
+        const float x = e.s0 * v;
+        if (n < e.split) {
+            e.o0[a0] = x;
+            e.o1[(unsigned)(r * e.ld1 + n)] = x * sig_hw(e.beta * e.i0[(unsigned)(r * e.ldi0 + n)]);
+        } else {
+            e.o2[(unsigned)(r * e.ld2 + (n - e.split))] = x;
+        }
+    } else if constexpr (MODE == E_RELU) {
+        e.o0[a0] = fmaxf(v + e.bias[n], 0.0f);
+    } else if constexpr (MODE == E_RGB) {
+        const float c = sig_hw(v + e.bias[n]);
+        e.o0[a0] = c;
+        e.o1[(unsigned)(r * e.ld1 + n)] = r < e.S ? e.drgb[(unsigned)(3 * r + n)] * c * (1.0f - c) : 0.0f;
+    } else if constexpr (MODE == E_MASK) {
+        e.o0[a0] = e.i0[(unsigned)(r * e.ldi0 + n)] > 0.0f ? v : 0.0f;
+    } else if constexpr (MODE == E_SO) {
+        const float sp = sig_hw(e.beta * e.i0[(unsigned)(r * e.ldi0 + n)]);
+        const float ee = e.i1 ? e.i1[(unsigned)(r * e.ldi1 + n)] : e.bias[n];
+        e.o0[a0] = v * sp;
+        e.o1[(unsigned)(r * e.ld1 + n)] = v * ee * (e.beta * sp * (1.0f - sp));
+    } else {   // E_FO
+        if (n < e.split)
+            e.o0[a0] = e.s0 * v * sig_hw(e.beta * e.i0[(unsigned)(r * e.ldi0 + n)]) +
+                       e.i1[(unsigned)(r * e.ldi1 + n)];
     }
-    if (st != rocblas_status_success) return st;
-    hipLaunchKernelGGL(k_splitk_reduce, dim3((unsigned)((sC + 255) / 256)), dim3(256), 0, g.st,
-                       g.part, nb, M, N, C, ldc);
-    return hipGetLastError() == hipSuccess ? rocblas_status_success : rocblas_status_internal_error;
 }
 
-// Row-major C[M,N] = alpha op(A) op(B) + beta C (op(A): [M,K], op(B): [K,N]).
-static rocblas_status gemm_rm(const Gemm &g, bool ta, bool tb, int M, int N, int K, float alpha,
-                              const float *A, int lda, const float *B, int ldb, float beta, float *C,
-                              int ldc) {
-    if (M == 0 || N == 0) return rocblas_status_success;
-    if (ta && !tb && alpha == 1.0f && beta == 1.0f && g.part && K >= 4 * kSplitRows &&
-        (size_t)splitk_chunks(K) * M * N <= g.part_cap)
-        return gemm_splitk(g, M, N, K, A, lda, B, ldb, C, ldc);
-    const rocblas_operation oa = ta ? rocblas_operation_transpose : rocblas_operation_none;
-    const rocblas_operation ob = tb ? rocblas_operation_transpose : rocblas_operation_none;
-    if (!g.bf16)
-        return rocblas_sgemm(g.h, ob, oa, N, M, K, &alpha, B, ldb, A, lda, &beta, C, ldc);
-    // stored extents of the row-major inputs
-    const size_t na = (size_t)(ta ? K : M) * lda, nb = (size_t)(tb ? N : K) * ldb;
-    if (na > g.cap || nb > g.cap) return rocblas_status_invalid_size;
-    to_bf16_dev(g.st, A, g.sa, (int64_t)na);
-    to_bf16_dev(g.st, B, g.sb, (int64_t)nb);
-    return rocblas_gemm_ex(g.h, ob, oa, N, M, K, &alpha, g.sb, rocblas_datatype_bf16_r, ldb, g.sa,
-                           rocblas_datatype_bf16_r, lda, &beta, C, rocblas_datatype_f32_r, ldc, C,
-                           rocblas_datatype_f32_r, ldc, rocblas_datatype_f32_r,
-                           rocblas_gemm_algo_standard, 0, 0);
+// grad f from the encoding rows: per row r, o0[3 r + a] = sum over the
+// encoding entries n of axis a of (v + i0[r, n]) i1[r, n], with v the
+// product (d f / d gamma through layer 0), i0 the skip layer's share and i1
+// the encoding's Jacobian.  The tile holds every column (one wave per row
+// block, BN >= N): each lane forms its columns' terms, then 32-lane
+// reductions per axis.
+template <int RB, int CB>
+__device__ __forceinline__ void epilogue_grad(const Epi &e, const bwd::Acc<RB, CB> &acc, int i0,
+                                              int M, int N) {
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int l32 = lane & 31, h = lane >> 5;
+#pragma unroll
+    for (int rb = 0; rb < RB; ++rb) {
+        const int r0 = i0 + (wave * RB + rb) * 32;
+#pragma unroll
+        for (int el = 0; el < 16; ++el) {
+            const int row = r0 + 8 * (el >> 2) + 4 * h + (el & 3);
+            float s3[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+            for (int cb = 0; cb < CB; ++cb) {
+                const int col = cb * 32 + l32;
+                float x = 0.0f;
+                if (row < M && col < N) {
+                    const unsigned a = (unsigned)(row * e.ldi0 + col);
+                    x = (acc.a[rb][cb][el] + (e.i0 ? e.i0[a] : 0.0f)) * e.i1[a];
+                }
+                const int ax = gamma_axis(col);
+                s3[0] += ax == 0 ? x : 0.0f;
+                s3[1] += ax == 1 ? x : 0.0f;
+                s3[2] += ax == 2 ? x : 0.0f;
+            }
+#pragma unroll
+            for (int m = 16; m >= 1; m >>= 1)
+#pragma unroll
+                for (int a = 0; a < 3; ++a) s3[a] += __shfl_xor(s3[a], m, 32);
+            if (l32 == 0 && row < M)
+#pragma unroll
+                for (int a = 0; a < 3; ++a) e.o0[(unsigned)(3 * row + a)] = s3[a];
+        }
+        __builtin_amdgcn_sched_barrier(0);
+    }
+}
+
+// the epilogue of a whole tile, its mode chosen once per workgroup
+template <int RB, int CB, int WC>
+__device__ __forceinline__ void epilogue(const Epi &e, const bwd::Acc<RB, CB> &acc, int i0, int j0,
+                                         int M, int N) {
+    if (e.mode == E_GRAD) {   // launched with one column tile of one wave's width
+        if constexpr (WC == 1) epilogue_grad<RB, CB>(e, acc, i0, M, N);
+        return;
+    }
+#define TSDFS_EPI_CASE(m)                                                                   \
+    case m:                                                                                 \
+        bwd::for_each<RB, CB, WC>(acc, i0, j0, M, N,                                        \
+                                  [&](int r, int n, float v) { apply<m>(e, r, n, v); });    \
+        break;
+    switch (e.mode) {
+        TSDFS_EPI_CASE(E_STORE)
+        TSDFS_EPI_CASE(E_BIAS)
+        TSDFS_EPI_CASE(E_SOFTPLUS)
+        TSDFS_EPI_CASE(E_REV)
+        TSDFS_EPI_CASE(E_RELU)
+        TSDFS_EPI_CASE(E_RGB)
+        TSDFS_EPI_CASE(E_MASK)
+        TSDFS_EPI_CASE(E_SO)
+        TSDFS_EPI_CASE(E_FO)
+    }
+#undef TSDFS_EPI_CASE
+}
+
+// -------------------------------------------------------------- products ----
+
+// Workgroup ids go round-robin over the 8 XCDs (each with its own L2).
+// Tiles that read the same rows (row products: the column tiles of one row
+// tile; weight gradients: the output tiles of one chunk) get ids that differ
+// by multiples of 8, so they share an XCD and its L2.
+constexpr int kXcd = 8;
+
+template <bool BF, int RB, int CB, int WC>
+__global__ void __launch_bounds__(bwd::kThreads) k_row(Opnd A, Opnd B, int R, int N, int j_base,
+                                                       int n_rt, int n_nt, Epi e) {
+    typedef bwd::Prec<BF> P;
+    constexpr int BN = WC * CB * 32;
+    __shared__ __attribute__((aligned(16))) typename P::T As[bwd::kBM * P::LS];
+    __shared__ __attribute__((aligned(16))) typename P::T Bs[BN * P::LS];
+    const int id = blockIdx.x, q = id / kXcd;
+    const int nt = q % n_nt, rt = (q / n_nt) * kXcd + id % kXcd;
+    if (rt >= n_rt) return;   // uniform over the workgroup
+    const int i0 = rt * bwd::kBM, j0 = j_base + nt * BN;
+    bwd::Acc<RB, CB> acc;
+    bwd::tile_product<BF, RB, CB, WC, bwd::LD_KVEC, bwd::LD_KVEC>(A, B, i0, j0, 0, A.n_k, acc, As,
+                                                                  Bs);
+    epilogue<RB, CB, WC>(e, acc, i0, j0, R, N);
+}
+
+// Weight gradients: partial products per chunk of rows; the workgroups of
+// the first column tile also form the chunk's column sums of A (the bias
+// gradients) when bpart is set.
+template <bool BF>
+__global__ void __launch_bounds__(bwd::kThreads, 2) k_wgrad(Opnd A, Opnd B, int M, int N, int R,
+                                                         int kc, int n_mt, int n_nt, int n_ch,
+                                                         float *__restrict__ part,
+                                                         float *__restrict__ bpart) {
+    typedef bwd::Prec<BF> P;
+    __shared__ __attribute__((aligned(16))) typename P::T As[bwd::kBM * P::LS];
+    __shared__ __attribute__((aligned(16))) typename P::T Bs[bwd::kBM * P::LS];
+    __shared__ float red[bwd::kThreads];
+    const int id = blockIdx.x, q = id / kXcd;
+    const int tile = q % (n_mt * n_nt), ch = (q / (n_mt * n_nt)) * kXcd + id % kXcd;
+    if (ch >= n_ch) return;   // uniform over the workgroup
+    const int nt = tile % n_nt;
+    const int i0 = (tile / n_nt) * bwd::kBM, j0 = nt * bwd::kBM;
+    const int k_begin = ch * kc, k_end = k_begin + kc < R ? k_begin + kc : R;
+    const bool sums = bpart != nullptr && nt == 0;
+    float a_sum = 0.0f;
+    bwd::Acc<2, 2> acc;
+    bwd::tile_product<BF, 2, 2, 2, bwd::LD_ICONT, bwd::LD_ICONT>(A, B, i0, j0, k_begin, k_end,
+                                                                 acc, As, Bs,
+                                                                 sums ? &a_sum : nullptr);
+    float *out = part + (size_t)ch * M * N;
+    bwd::for_each<2, 2, 2>(acc, i0, j0, M, N,
+                           [&](int m, int n, float v) { out[(unsigned)(m * N + n)] = v; });
+    if (sums) {   // rows tid and tid + 128 of the tile hold the same A row
+        const int tid = threadIdx.x;
+        red[tid] = a_sum;
+        __syncthreads();
+        if (tid < bwd::kBM && i0 + tid < M)
+            bpart[(size_t)ch * M + i0 + tid] = red[tid] + red[tid + bwd::kBM];
+    }
+}
+
+// C[r ldc + c] += sum over the nb chunks of part[b][r N + c] (r N + c < mn),
+// in a fixed order: chunk b goes to accumulator b % 8 (independent loads in
+// flight), then the eight are added pairwise.
+__global__ void __launch_bounds__(256) k_chunk_reduce(const float *__restrict__ part, int nb,
+                                                      int mn, int N, float *__restrict__ C,
+                                                      int ldc) {
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= mn) return;
+    float a[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    int b = 0;
+    for (; b + 8 <= nb; b += 8)
+#pragma unroll
+        for (int u = 0; u < 8; ++u) a[u] += part[(size_t)(b + u) * mn + i];
+    for (int u = 0; b + u < nb; ++u) a[u] += part[(size_t)(b + u) * mn + i];
+    const float s = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
+    const int r = i / N, c = i - r * N;
+    C[(unsigned)(r * ldc + c)] += s;
+}
+
+// Chunks of the weight-gradient reduction: at most kMaxChunks, at least 512
+// rows each (a multiple of both K steps).
+constexpr int kMaxChunks = 256;
+static int chunk_rows(int R) {
+    int kc = (R + kMaxChunks - 1) / kMaxChunks;
+    kc = (kc + 63) / 64 * 64;
+    return kc < 512 ? 512 : kc;
+}
+
+struct Ctx {
+    hipStream_t st;
+    bool bf16;
+    float *part;        // weight-gradient partials
+    size_t part_cap;    // floats in part
+    float *bpart;       // bias-gradient partials [kMaxChunks][<= wide]
+};
+
+static bool vec_ok(const float *p, int ld, int k) {
+    return ((uintptr_t)p % 16 == 0) && ld % 4 == 0 && ld >= round4(k);
+}
+
+// Columns [j_base, j_base + ncols) of a row product in tiles of 32 NB.
+template <bool BF>
+static void launch_row(const Ctx &c, int nb, const Opnd &A, const Opnd &B, int R, int N,
+                       int j_base, int ncols, const Epi &e) {
+    const int n_rt = (R + bwd::kBM - 1) / bwd::kBM;
+    const int n_nt = (ncols + 32 * nb - 1) / (32 * nb);
+    const unsigned grid = (unsigned)((n_rt + kXcd - 1) / kXcd * kXcd * n_nt);
+    if (nb == 4)
+        hipLaunchKernelGGL((k_row<BF, 2, 2, 2>), dim3(grid), dim3(bwd::kThreads), 0, c.st, A, B, R,
+                           N, j_base, n_rt, n_nt, e);
+    else if (nb == 2)
+        hipLaunchKernelGGL((k_row<BF, 1, 2, 1>), dim3(grid), dim3(bwd::kThreads), 0, c.st, A, B, R,
+                           N, j_base, n_rt, n_nt, e);
+    else
+        hipLaunchKernelGGL((k_row<BF, 1, 1, 1>), dim3(grid), dim3(bwd::kThreads), 0, c.st, A, B, R,
+                           N, j_base, n_rt, n_nt, e);
+}
+
+template <bool BF>
+static void row_tiles(const Ctx &c, const Opnd &A, const Opnd &B, int R, int N, const Epi &e) {
+    const int nfull = N / 128 * 128, rem = N - nfull;
+    if (nfull > 0) launch_row<BF>(c, 4, A, B, R, N, 0, nfull, e);
+    if (rem > 0) launch_row<BF>(c, rem <= 32 ? 1 : rem <= 64 ? 2 : 4, A, B, R, N, nfull, rem, e);
+}
+
+// C[r][n] (r < R, n < N) = sum_{k < K} A[r lda + k] W[n ldw + k] through the
+// epilogue e.  Both operands must allow 16-byte loads (vec_ok): activations
+// have padded rows, weights are the staged copies.
+static int gemm_row(const Ctx &c, int R, int N, int K, const float *A, int lda, const float *W,
+                    int ldw, const Epi &e) {
+    if (R <= 0 || N <= 0) return TSDFS_OK;
+    if (!vec_ok(A, lda, K) || !vec_ok(W, ldw, K)) {
+        set_error("internal: row product operands not aligned (ld %d / %d, K %d)", lda, ldw, K);
+        return TSDFS_EHIP;
+    }
+    const Opnd a{A, lda, R, K};
+    const Opnd b{W, ldw, N, K};
+    if (c.bf16)
+        row_tiles<true>(c, a, b, R, N, e);
+    else
+        row_tiles<false>(c, a, b, R, N, e);
+    TSDFS_LAUNCH_CHECK();
+    return TSDFS_OK;
+}
+
+// C[m ldc + n] += sum_{r < R} A[r lda + m] B[r ldb + n]  (m < M, n < N), and
+// with bias: bias[m] += sum_{r < R} A[r lda + m]
+static int gemm_wgrad(const Ctx &c, int R, int M, int N, const float *A, int lda, const float *B,
+                      int ldb, float *C, int ldc, float *bias = nullptr) {
+    if (R <= 0 || M <= 0 || N <= 0) return TSDFS_OK;
+    const int kc = chunk_rows(R), n_ch = (R + kc - 1) / kc;
+    const int n_mt = (M + bwd::kBM - 1) / bwd::kBM, n_nt = (N + bwd::kBM - 1) / bwd::kBM;
+    if ((size_t)n_ch * M * N > c.part_cap) {
+        set_error("internal: weight-gradient partials exceed the workspace");
+        return TSDFS_EHIP;
+    }
+    const Opnd a{A, lda, M, R};
+    const Opnd b{B, ldb, N, R};
+    const unsigned grid = (unsigned)((n_ch + kXcd - 1) / kXcd * kXcd * n_mt * n_nt);
+    float *bp = bias ? c.bpart : nullptr;
+    if (c.bf16)
+        hipLaunchKernelGGL(k_wgrad<true>, dim3(grid), dim3(bwd::kThreads), 0, c.st, a, b, M, N, R,
+                           kc, n_mt, n_nt, n_ch, c.part, bp);
+    else
+        hipLaunchKernelGGL(k_wgrad<false>, dim3(grid), dim3(bwd::kThreads), 0, c.st, a, b, M, N, R,
+                           kc, n_mt, n_nt, n_ch, c.part, bp);
+    const int mn = M * N;
+    hipLaunchKernelGGL(k_chunk_reduce, dim3((unsigned)((mn + 255) / 256)), dim3(256), 0, c.st,
+                       c.part, n_ch, mn, N, C, ldc);
+    if (bias)
+        hipLaunchKernelGGL(k_chunk_reduce, dim3((unsigned)((M + 255) / 256)), dim3(256), 0, c.st,
+                           c.bpart, n_ch, M, M, bias, 0);
+    TSDFS_LAUNCH_CHECK();
+    return TSDFS_OK;
 }
 
 // y[N] += sum over the rows of row-major A[R,N] (ld): per block of 64
@@ -201,125 +423,64 @@ __global__ void k_colsum_fin(const float *__restrict__ part, int n_chunks, int N
 
 static int colsum_chunks(int R) { return (R + kColsumChunk - 1) / kColsumChunk; }
 
-static rocblas_status colsum(hipStream_t st, int R, int N, const float *A, int ld, float *part,
-                             float *y) {
-    if (R <= 0 || N <= 0) return rocblas_status_success;
+static int colsum(hipStream_t st, int R, int N, const float *A, int ld, float *part, float *y) {
+    if (R <= 0 || N <= 0) return TSDFS_OK;
     const int nch = colsum_chunks(R);
     hipLaunchKernelGGL(k_colsum_part, dim3((N + 63) / 64, nch), dim3(256), 0, st, A, R, N, ld,
                        part);
     hipLaunchKernelGGL(k_colsum_fin, dim3((N + 255) / 256), dim3(256), 0, st, part, nch, N, y);
-    return hipGetLastError() == hipSuccess ? rocblas_status_success : rocblas_status_internal_error;
+    TSDFS_LAUNCH_CHECK();
+    return TSDFS_OK;
 }
 
-// ------------------------------------------------------------- compositing --
-
-__device__ __forceinline__ float logsig_t(float x) {
-    return x >= 0.0f ? -log1pf(expf(-x)) : x - log1pf(expf(x));
-}
-
-// Adjoint of the NeuS compositing of rgb: given d rgb_out per ray, the
-// gradients w.r.t. each sample's f, grad f and rgb.
-__global__ void k_composite_bwd(const int32_t *__restrict__ offsets, int64_t n_rays,
-                                const float *__restrict__ v, const float *__restrict__ dt,
-                                const float *__restrict__ f, const float *__restrict__ g,
-                                const float *__restrict__ rgb, float s,
-                                const float *__restrict__ d_out, float *__restrict__ d_f,
-                                float *__restrict__ d_g, float *__restrict__ d_rgb) {
-    int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (r >= n_rays) return;
-    const int32_t j0 = offsets[r], j1 = offsets[r + 1];
-    const float vx = v[3 * r], vy = v[3 * r + 1], vz = v[3 * r + 2];
-    const float dc0 = d_out[3 * r], dc1 = d_out[3 * r + 1], dc2 = d_out[3 * r + 2];
-    // forward: total of w_i (dC . c_i) for the suffix sums
-    float logT = 0.0f, total = 0.0f;
-    for (int32_t j = j0; j < j1; ++j) {
-        float cosv = fminf(vx * g[3 * j] + vy * g[3 * j + 1] + vz * g[3 * j + 2], 0.0f);
-        float half = 0.5f * cosv * dt[j];
-        float L = fminf(logsig_t(s * (f[j] + half)) - logsig_t(s * (f[j] - half)), 0.0f);
-        float w = expf(logT) * (-expm1f(L));
-        total += w * (dc0 * rgb[3 * j] + dc1 * rgb[3 * j + 1] + dc2 * rgb[3 * j + 2]);
-        logT += L;
+// *out = sum of x[0 .. n) by one workgroup in a fixed order
+__global__ void __launch_bounds__(256) k_sum_fixed(const float *__restrict__ x, int n,
+                                                   float *__restrict__ out) {
+    __shared__ float red[256];
+    float s = 0.0f;
+    for (int i = threadIdx.x; i < n; i += 256) s += x[i];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int k = 128; k > 0; k >>= 1) {
+        if (threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
+        __syncthreads();
     }
-    // backward: dL_j = -(1 - alpha_j) T_j (dC.c_j) + sum_{i>j} w_i (dC.c_i)
-    logT = 0.0f;
-    float done = 0.0f;   // sum_{i<=j} w_i (dC.c_i)
-    for (int32_t j = j0; j < j1; ++j) {
-        float gx = g[3 * j], gy = g[3 * j + 1], gz = g[3 * j + 2];
-        float cv = vx * gx + vy * gy + vz * gz;
-        float cosv = fminf(cv, 0.0f);
-        float fj = f[j], dtj = dt[j];
-        float half = 0.5f * cosv * dtj;
-        float xn = s * (fj + half), xp = s * (fj - half);
-        float L = fminf(logsig_t(xn) - logsig_t(xp), 0.0f);
-        float T = expf(logT);
-        float alpha = -expm1f(L);
-        float w = T * alpha;
-        float dcj = dc0 * rgb[3 * j] + dc1 * rgb[3 * j + 1] + dc2 * rgb[3 * j + 2];
-        done += w * dcj;
-        float dL = -(1.0f - alpha) * T * dcj + (total - done);
-        // L = logsig(xn) - logsig(xp), d logsig(x)/dx = sigmoid(-x)
-        float dxn = dL * sig(-xn), dxp = -dL * sig(-xp);
-        float dfn = s * dxn, dfp = s * dxp;
-        d_f[j] = dfn + dfp;
-        float dcos = (dfn - dfp) * 0.5f * dtj;
-        float dcv = cv < 0.0f ? dcos : 0.0f;
-        d_g[3 * j] = dcv * vx;
-        d_g[3 * j + 1] = dcv * vy;
-        d_g[3 * j + 2] = dcv * vz;
-        d_rgb[3 * j] = w * dc0;
-        d_rgb[3 * j + 1] = w * dc1;
-        d_rgb[3 * j + 2] = w * dc2;
-        logT += L;
-    }
-}
-
-// loss = (1/B) sum_rays |C - C*|^2 ; d C = 2 (C - C*) / B
-__global__ void k_rgb_loss(const float *__restrict__ rgb, const float *__restrict__ target,
-                           int64_t n_rays, float *__restrict__ d_rgb, float *__restrict__ loss) {
-    int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    float l = 0.0f;
-    if (r < n_rays) {
-        for (int a = 0; a < 3; ++a) {
-            float d = rgb[3 * r + a] - target[3 * r + a];
-            l += d * d;
-            d_rgb[3 * r + a] = 2.0f * d / (float)n_rays;
-        }
-    }
-    for (int off = 32; off > 0; off >>= 1) l += __shfl_xor(l, off);
-    if ((threadIdx.x & 63) == 0 && loss) atomicAdd(loss, l / (float)n_rays);
+    if (threadIdx.x == 0) *out = red[0];
 }
 
 // ------------------------------------------------------- network backward --
 
 struct BwdBufs {
-    int R, S, P, W, dg, cin;
-    float *xh, *vr, *gam, *J;             // [R,3], [R,3], [R,dg], [R,dg]
-    float *X[kMaxHidden + 1];             // inputs of SDF layers (X[n_hidden] = H_last)
+    int R, S, P, W, dg, ldg, cin, ldc, ny, ldy, wide;
+    float *xh, *vr, *gam, *J;             // [R,3], [R,3], [R,ldg], [R,ldg]
+    float *X[kMaxHidden + 1];             // inputs of SDF layers (X[0] = gam, X[n_hidden] = H_last)
     float *Z[kMaxHidden];                 // pre-activations (bias added)
     float *D[kMaxHidden];                 // delta_l
     float *E[kMaxHidden];                 // E_l = delta_{l+1} W_{l+1} (l < n_hidden - 1)
-    float *Eg0, *Eg4;                      // encoding rows of the reverse pass [R,dg]
-    float *Y;                              // output layer [R, 1 + n_feat]
-    float *g;                              // grad f [R,3]
-    float *Cin;                            // colour input [R, cin]
-    float *Zc[kMaxColor], *Hc[kMaxColor];  // colour pre/post activations
-    float *zo, *rgb;                       // [R,3]
-    float *gbar, *gbar_g;                  // [R,3], [R,dg]
-    float *Ybar;                           // [R, 1 + n_feat]
-    float *T0, *T1, *T2, *T3;             // scratch [R, max(cin, W+1)]
-    float *Z2[kMaxHidden];                 // second-order contributions
-    float *part;                           // column-sum partials [ceil(R/1024)][wide]
-    float *splitk;                         // split-K partials [ceil(R/2048)][wide][wide]
+    float *Z2[kMaxHidden];                // second-order contributions
+    float *Eg4;                           // skip layer's encoding rows of the reverse pass [R,ldg]
+    float *Y;                             // output layer [R, ldy]
+    float *g;                             // grad f [R,3]
+    float *Cin;                           // colour input [R, ldc]
+    float *Hc[kMaxColor];                 // colour activations [R, W]
+    float *rgb, *dz;                      // [R,4]
+    float *gbar_g;                        // [R, ldg]
+    float *Ybar;                          // [R, ldy]
+    float *T0, *T1, *T2;                  // scratch [R, wide]
+    float *eik;                           // per-row eikonal loss [R]
+    float *part;                          // column-sum partials [ceil(R/1024)][wide]
+    float *splitk;                        // weight-gradient partials
     size_t splitk_cap;
-    float *loss;                           // [2] eikonal loss (device)
-    __bf16 *ca, *cb;                       // BF16 copies of product inputs [bf16_cap]
-    size_t bf16_cap;
+    float *bpart;                         // bias-gradient partials [kMaxChunks][wide]
+    // the weights staged for 16-byte loads: W [out][round4(in)] and its
+    // transpose [in][round4(out)], per SDF layer (output layer last) and
+    // per colour layer (rgb layer last)
+    float *Wn[kMaxHidden + 1], *Wt[kMaxHidden + 1];
+    float *Cn[kMaxColor + 1], *Ct[kMaxColor + 1];
 };
 
 static size_t carve(BwdBufs &b, const tsdfs_field *F, int R, char *base) {
     const int W = F->desc.width, nh = F->desc.n_hidden;
-    const int dg = F->plan.d_gamma, cin = 9 + F->desc.n_feat;
-    const int wide = (cin > W + 1 ? cin : W + 1);
     size_t off = 0;
     auto take = [&](size_t n) -> float * {
         float *p = base ? (float *)(base + off) : nullptr;
@@ -328,12 +489,18 @@ static size_t carve(BwdBufs &b, const tsdfs_field *F, int R, char *base) {
     };
     b.R = R;
     b.W = W;
-    b.dg = dg;
-    b.cin = cin;
+    b.dg = F->plan.d_gamma;
+    b.ldg = round4(b.dg);
+    b.cin = 9 + F->desc.n_feat;
+    b.ldc = round4(b.cin);
+    b.ny = 1 + F->desc.n_feat;
+    b.ldy = round4(b.ny);
+    b.wide = b.ldc > b.ldy ? b.ldc : b.ldy;
+    if (W > b.wide) b.wide = W;
     b.xh = take((size_t)R * 3);
     b.vr = take((size_t)R * 3);
-    b.gam = take((size_t)R * dg);
-    b.J = take((size_t)R * dg);
+    b.gam = take((size_t)R * b.ldg);
+    b.J = take((size_t)R * b.ldg);
     for (int l = 0; l <= nh; ++l) b.X[l] = l == 0 ? b.gam : take((size_t)R * W);
     for (int l = 0; l < nh; ++l) {
         b.Z[l] = take((size_t)R * W);
@@ -341,69 +508,55 @@ static size_t carve(BwdBufs &b, const tsdfs_field *F, int R, char *base) {
         b.E[l] = take((size_t)R * W);
         b.Z2[l] = take((size_t)R * W);
     }
-    b.Eg0 = take((size_t)R * dg);
-    b.Eg4 = take((size_t)R * dg);
-    b.Y = take((size_t)R * (1 + F->desc.n_feat));
+    b.Eg4 = take((size_t)R * b.ldg);
+    b.Y = take((size_t)R * b.ldy);
     b.g = take((size_t)R * 3);
-    b.Cin = take((size_t)R * cin);
-    for (int l = 0; l < F->desc.col_hidden; ++l) {
-        b.Zc[l] = take((size_t)R * W);
-        b.Hc[l] = take((size_t)R * W);
-    }
-    b.zo = take((size_t)R * 3);
-    b.rgb = take((size_t)R * 3);
-    b.gbar = take((size_t)R * 3);
-    b.gbar_g = take((size_t)R * dg);
-    b.Ybar = take((size_t)R * (1 + F->desc.n_feat));
-    b.T0 = take((size_t)R * wide);
-    b.T1 = take((size_t)R * wide);
-    b.T2 = take((size_t)R * wide);
-    b.T3 = take((size_t)R * wide);
-    b.part = take((size_t)colsum_chunks(R) * wide);
-    b.splitk_cap = (size_t)splitk_chunks(R) * wide * wide;
+    b.Cin = take((size_t)R * b.ldc);
+    for (int l = 0; l < F->desc.col_hidden; ++l) b.Hc[l] = take((size_t)R * W);
+    b.rgb = take((size_t)R * 4);
+    b.dz = take((size_t)R * 4);
+    b.gbar_g = take((size_t)R * b.ldg);
+    b.Ybar = take((size_t)R * b.ldy);
+    b.T0 = take((size_t)R * b.wide);
+    b.T1 = take((size_t)R * b.wide);
+    b.T2 = take((size_t)R * b.wide);
+    b.eik = take((size_t)(R > 0 ? R : 1));
+    b.part = take((size_t)colsum_chunks(R) * b.wide);
+    const int kc = chunk_rows(R);
+    b.splitk_cap = (size_t)((R + kc - 1) / kc) * (W + 1) * b.wide;
     b.splitk = take(b.splitk_cap);
-    b.loss = take(2);
-    // every product input is an [R or <= 272 rows][<= 272] row-major block
-    b.bf16_cap = (size_t)(R > kMaxRows ? R : kMaxRows) * (kMaxRows + 8);
-    b.ca = (__bf16 *)take((b.bf16_cap + 1) / 2);
-    b.cb = (__bf16 *)take((b.bf16_cap + 1) / 2);
+    b.bpart = take((size_t)kMaxChunks * b.wide);
+    for (int l = 0; l <= nh; ++l) {
+        b.Wn[l] = take((size_t)F->dout[l] * round4(F->din[l]));
+        b.Wt[l] = take((size_t)F->din[l] * round4(F->dout[l]));
+    }
+    for (int l = 0; l <= F->desc.col_hidden; ++l) {
+        b.Cn[l] = take((size_t)F->cdout[l] * round4(F->cdin[l]));
+        b.Ct[l] = take((size_t)F->cdin[l] * round4(F->cdout[l]));
+    }
     return off;
 }
 
-#define BLAS(call)                                                         \
-    do {                                                                   \
-        rocblas_status st_ = (call);                                       \
-        if (st_ != rocblas_status_success) {                               \
-            set_error("rocBLAS call failed (%d): %s", (int)st_, #call);    \
-            return TSDFS_EHIP;                                             \
-        }                                                                  \
+#define BWD(call)                      \
+    do {                               \
+        int rc_ = (call);              \
+        if (rc_ != TSDFS_OK) return rc_; \
     } while (0)
 
-static int network_backward(tsdfs_field *F, const float *o, const float *v, const float *t,
+static int network_backward(const tsdfs_field *F, const float *o, const float *v, const float *t,
                             const int32_t *ray_id, int64_t S, const float *eik_x, int64_t P,
                             float eik_lambda, const float *d_f, const float *d_grad,
                             const float *d_rgb, float *gs, float *gc, char *ws, hipStream_t st,
                             float *eik_loss_out, bool bf16) {
-    if (!F->blas) {
-        rocblas_handle h;
-        if (rocblas_create_handle(&h) != rocblas_status_success) {
-            set_error("rocblas_create_handle failed");
-            return TSDFS_EHIP;
-        }
-        F->blas = h;
-    }
-    rocblas_handle h = (rocblas_handle)F->blas;
-    BLAS(rocblas_set_stream(h, st));
-    BLAS(rocblas_set_pointer_mode(h, rocblas_pointer_mode_host));
     const int R = (int)(S + P);
     BwdBufs B;
     carve(B, F, R, ws);
     B.S = (int)S;
     B.P = (int)P;
-    const Gemm G{h, st, bf16, B.ca, B.cb, B.bf16_cap, B.splitk, B.splitk_cap};
+    const Ctx C{st, bf16, B.splitk, B.splitk_cap, B.bpart};
     const tsdfs_field_desc &d = F->desc;
-    const Plan &PL = F->plan;
-    const int W = d.width, nh = d.n_hidden, dg = B.dg, cin = B.cin, nf = d.n_feat;
+    const int W = d.width, nh = d.n_hidden, dg = B.dg, ldg = B.ldg, cin = B.cin, ldc = B.ldc;
+    const int nf = d.n_feat, ny = B.ny, ldy = B.ldy;
     const int skip = d.skip_at;
     const float beta = d.beta, scale = d.scale;
     const float cx = d.center[0], cy = d.center[1], cz = d.center[2];
@@ -413,10 +566,28 @@ static int network_backward(tsdfs_field *F, const float *o, const float *v, cons
     auto bl = [&](int l) { return Ws + F->b_off[l]; };
     auto gW = [&](int l) { return gs + F->w_off[l]; };
     auto gb = [&](int l) { return gs + F->b_off[l]; };
+    const float *wf = Wl(nh);   // row 0 of the output layer: the f row
+    // staged weights: Wn = W with rows padded to 4 floats, Wt = W^T likewise
+    auto stage = [&](const float *Wsrc, int out, int in, float *Wn_, float *Wt_) {
+        const int ldn = round4(in), ldt = round4(out);
+        map2(out, in, st, [=] __device__(int o_, int i_) {
+            const float w = Wsrc[(unsigned)(o_ * in + i_)];
+            Wn_[(unsigned)(o_ * ldn + i_)] = w;
+            Wt_[(unsigned)(i_ * ldt + o_)] = w;
+        });
+    };
+    for (int l = 0; l <= nh; ++l) stage(Wl(l), F->dout[l], F->din[l], B.Wn[l], B.Wt[l]);
+    for (int l = 0; l <= d.col_hidden; ++l)
+        stage(Wc + F->cw_off[l], F->cdout[l], F->cdin[l], B.Cn[l], B.Ct[l]);
+    auto ldn = [&](int l) { return round4(F->din[l]); };    // Wn[l]
+    auto ldt = [&](int l) { return round4(F->dout[l]); };   // Wt[l]
+    auto cldn = [&](int l) { return round4(F->cdin[l]); };  // Cn[l]
+    auto cldt = [&](int l) { return round4(F->cdout[l]); }; // Ct[l]
 
-    // ---- inputs: x_hat, direction, encoding and its Jacobian; loss = 0
+    // ---- inputs: x_hat and direction per row, then the encoding and its
+    // Jacobian per (row, encoding entry)
     {
-        float *xh = B.xh, *vr = B.vr, *gam = B.gam, *J = B.J, *loss = B.loss;
+        float *xh = B.xh, *vr = B.vr;
         const int Si = (int)S;
         map((int64_t)R, st, [=] __device__(int64_t r) {
             float p[3], vv[3];
@@ -434,268 +605,298 @@ static int network_backward(tsdfs_field *F, const float *o, const float *v, cons
             }
             float c[3] = {cx, cy, cz};
             for (int a = 0; a < 3; ++a) {
-                float x = (p[a] - c[a]) / scale;
-                xh[3 * r + a] = x;
+                xh[3 * r + a] = (p[a] - c[a]) / scale;
                 vr[3 * r + a] = vv[a];
             }
-            for (int j = 0; j < dg; ++j) {
-                int a = gamma_axis(j);
-                float x = xh[3 * r + a];
-                if (j < 3) {
-                    gam[(int64_t)r * dg + j] = x;
-                    J[(int64_t)r * dg + j] = 1.0f;
-                } else {
-                    int k = (j - 3) / 6, rem = (j - 3) % 6;
-                    float sc = ldexpf(1.0f, k), y = sc * x;
-                    gam[(int64_t)r * dg + j] = rem < 3 ? sinf(y) : cosf(y);
-                    J[(int64_t)r * dg + j] = rem < 3 ? sc * cosf(y) : -sc * sinf(y);
-                }
+        });
+        float *gam = B.gam, *J = B.J;
+        map2(R, dg, st, [=] __device__(int r, int j) {
+            const float x = xh[3 * r + gamma_axis(j)];
+            const unsigned a = (unsigned)(r * ldg + j);
+            if (j < 3) {
+                gam[a] = x;
+                J[a] = 1.0f;
+            } else {
+                const int k = (j - 3) / 6, rem = (j - 3) % 6;
+                const float sc = ldexpf(1.0f, k), y = sc * x;
+                float sn, cs;
+                sincosf(y, &sn, &cs);
+                gam[a] = rem < 3 ? sn : cs;
+                J[a] = rem < 3 ? sc * cs : -sc * sn;
             }
-            if (r < 2) loss[r] = 0.0f;
         });
     }
-    // ---- SDF forward
+    // ---- SDF forward: Z_l, X_{l+1} = softplus(Z_l) (x 1/sqrt2 into the skip
+    // layer), and for the last hidden layer delta = w_f softplus'(Z)
     for (int l = 0; l < nh; ++l) {
         const int in = F->din[l], out = F->dout[l];
-        BLAS(gemm_rm(G, false, true, R, out, in, 1.0f, B.X[l], in, Wl(l), in, 0.0f, B.Z[l], W));
-        float *Z = B.Z[l], *Xn = B.X[l + 1];
-        const float *bb = bl(l);
         const bool to_skip = (l + 1 == skip);
-        const float hs = to_skip ? rs2 : 1.0f;
-        map((int64_t)R * out, st, [=] __device__(int64_t i) {
-            int64_t r = i / out;
-            int j = (int)(i - r * out);
-            float z = Z[r * W + j] + bb[j];
-            Z[r * W + j] = z;
-            Xn[r * W + j] = hs * softplus_b(z, beta);
-        });
+        Epi e;
+        e.mode = E_SOFTPLUS;
+        e.o0 = B.Z[l];
+        e.ld0 = W;
+        e.o1 = B.X[l + 1];
+        e.ld1 = W;
+        e.bias = bl(l);
+        e.beta = beta;
+        e.ln2_beta = kLn2 / beta;
+        e.s0 = to_skip ? rs2 : 1.0f;
+        if (l == nh - 1) {
+            e.o2 = B.D[nh - 1];
+            e.ld2 = W;
+            e.i0 = wf;
+        }
+        BWD(gemm_row(C, R, out, in, B.X[l], l == 0 ? ldg : W, B.Wn[l], ldn(l), e));
         if (to_skip) {
+            float *Xn = B.X[l + 1];
             const float *gam = B.gam;
-            map((int64_t)R * dg, st, [=] __device__(int64_t i) {
-                int64_t r = i / dg;
-                int j = (int)(i - r * dg);
-                Xn[r * W + out + j] = rs2 * gam[i];
+            map2(R, dg, st, [=] __device__(int r, int j) {
+                Xn[(size_t)r * W + out + j] = rs2 * gam[(size_t)r * ldg + j];
             });
         }
     }
     // output layer Y = X_last W_out^T + b_out
-    const int ny = 1 + nf;
-    BLAS(gemm_rm(G, false, true, R, ny, W, 1.0f, B.X[nh], W, Wl(nh), W, 0.0f, B.Y, ny));
     {
-        float *Y = B.Y;
-        const float *bb = bl(nh);
-        map((int64_t)R * ny, st, [=] __device__(int64_t i) { Y[i] += bb[i % ny]; });
+        Epi e;
+        e.mode = E_BIAS;
+        e.o0 = B.Y;
+        e.ld0 = ldy;
+        e.bias = bl(nh);
+        BWD(gemm_row(C, R, ny, W, B.X[nh], W, B.Wn[nh], ldn(nh), e));
     }
-    // ---- reverse pass: delta_{L-1} = w_f * softplus'(z), E_{l-1} = delta_l W_l
-    {
-        float *D = B.D[nh - 1];
-        const float *Z = B.Z[nh - 1], *wf = Wl(nh);
-        map((int64_t)R * W, st, [=] __device__(int64_t i) {
-            int j = (int)(i % W);
-            D[i] = wf[j] * sig(beta * Z[i]);
-        });
-    }
+    // ---- reverse pass: E_{l-1} = delta_l W_l (x 1/sqrt2 out of the skip
+    // layer), delta_{l-1} = E_{l-1} softplus'(Z_{l-1}); encoding rows apart
     for (int l = nh - 1; l >= 1; --l) {
         const int in = F->din[l], out = F->dout[l];
-        // E' = delta_l W_l : [R, in]
-        BLAS(gemm_rm(G, false, false, R, in, out, 1.0f, B.D[l], W, Wl(l), in, 0.0f, B.T0, W));
-        const int np = F->dout[l - 1];
-        const bool sk = (l == skip);
-        float *E = B.E[l - 1], *Dm = B.D[l - 1], *Eg4 = B.Eg4, *T0 = B.T0;
-        const float *Zm = B.Z[l - 1];
-        const float es = sk ? rs2 : 1.0f;
-        map((int64_t)R * in, st, [=] __device__(int64_t i) {
-            int64_t r = i / in;
-            int j = (int)(i - r * in);
-            float e = es * T0[r * W + j];
-            if (j < np) {
-                E[r * W + j] = e;
-                Dm[r * W + j] = e * sig(beta * Zm[r * W + j]);
-            } else {
-                Eg4[r * dg + (j - np)] = e;
-            }
-        });
+        Epi e;
+        e.mode = E_REV;
+        e.s0 = (l == skip) ? rs2 : 1.0f;
+        e.split = F->dout[l - 1];
+        e.o0 = B.E[l - 1];
+        e.ld0 = W;
+        e.o1 = B.D[l - 1];
+        e.ld1 = W;
+        e.i0 = B.Z[l - 1];
+        e.ldi0 = W;
+        e.o2 = B.Eg4;
+        e.ld2 = ldg;
+        e.beta = beta;
+        BWD(gemm_row(C, R, in, out, B.D[l], W, B.Wt[l], ldt(l), e));
     }
-    // encoding rows from layer 0: Eg0 = delta_0 W_0 : [R, dg]
-    BLAS(gemm_rm(G, false, false, R, dg, F->dout[0], 1.0f, B.D[0], W, Wl(0), dg, 0.0f, B.Eg0, dg));
+    // encoding rows from layer 0, delta_0 W_0 [R, dg], and with the skip
+    // layer's share and the encoding's Jacobian, grad f (in the epilogue)
     {
-        float *g = B.g;
-        const float *J = B.J, *Eg0 = B.Eg0, *Eg4 = B.Eg4;
-        const bool has_skip = skip > 0;
-        map((int64_t)R, st, [=] __device__(int64_t r) {
-            float acc3[3] = {0.f, 0.f, 0.f};
-            for (int j = 0; j < dg; ++j) {
-                float e = Eg0[r * dg + j] + (has_skip ? Eg4[r * dg + j] : 0.0f);
-                acc3[gamma_axis(j)] += e * J[r * dg + j];
-            }
-            for (int a = 0; a < 3; ++a) g[3 * r + a] = acc3[a];
-        });
+        if (dg > 64) {
+            set_error("internal: encoding wider than 64");
+            return TSDFS_EHIP;
+        }
+        Epi e;
+        e.mode = E_GRAD;
+        e.o0 = B.g;
+        e.i0 = skip > 0 ? B.Eg4 : nullptr;
+        e.ldi0 = ldg;
+        e.i1 = B.J;
+        e.ldi1 = ldg;
+        BWD(gemm_row(C, R, dg, F->dout[0], B.D[0], W, B.Wt[0], ldt(0), e));
     }
     // ---- colour forward
     {
         float *Cin = B.Cin;
         const float *xh = B.xh, *vr = B.vr, *g = B.g, *Y = B.Y;
-        map((int64_t)R * cin, st, [=] __device__(int64_t i) {
-            int64_t r = i / cin;
-            int j = (int)(i - r * cin);
+        map2(R, cin, st, [=] __device__(int r, int j) {
             float x;
             if (j < 3) x = xh[3 * r + j];
             else if (j < 6) x = vr[3 * r + j - 3];
             else if (j < 9) x = g[3 * r + j - 6];
-            else x = Y[r * ny + 1 + (j - 9)];
-            Cin[i] = x;
+            else x = Y[(size_t)r * ldy + 1 + (j - 9)];
+            Cin[(size_t)r * ldc + j] = x;
         });
     }
     const int nc = d.col_hidden;
     for (int l = 0; l < nc; ++l) {
         const int in = F->cdin[l];
-        const float *X = l == 0 ? B.Cin : B.Hc[l - 1];
-        BLAS(gemm_rm(G, false, true, R, W, in, 1.0f, X, in, Wc + F->cw_off[l], in, 0.0f, B.Zc[l], W));
-        float *Z = B.Zc[l], *H = B.Hc[l];
-        const float *bb = Wc + F->cb_off[l];
-        map((int64_t)R * W, st, [=] __device__(int64_t i) {
-            float z = Z[i] + bb[i % W];
-            Z[i] = z;
-            H[i] = fmaxf(z, 0.0f);
-        });
+        Epi e;
+        e.mode = E_RELU;
+        e.o0 = B.Hc[l];
+        e.ld0 = W;
+        e.bias = Wc + F->cb_off[l];
+        BWD(gemm_row(C, R, W, in, l == 0 ? B.Cin : B.Hc[l - 1], l == 0 ? ldc : W, B.Cn[l],
+                     cldn(l), e));
     }
-    BLAS(gemm_rm(G, false, true, R, 3, W, 1.0f, B.Hc[nc - 1], W, Wc + F->cw_off[nc], W, 0.0f, B.zo, 3));
-    // ---- colour backward: dz_out = d rgb * rgb (1 - rgb)
+    // rgb = sigmoid(H W^T + b); dz_out = d rgb * rgb (1 - rgb) on sample rows
     {
-        float *zo = B.zo, *rgb = B.rgb, *dz = B.T0;
-        const float *bb = Wc + F->cb_off[nc];
-        const int Si = (int)S;
-        map((int64_t)R * 3, st, [=] __device__(int64_t i) {
-            int64_t r = i / 3;
-            float c = sig(zo[i] + bb[i % 3]);
-            rgb[i] = c;
-            dz[i] = r < Si ? d_rgb[i] * c * (1.0f - c) : 0.0f;
-        });
+        Epi e;
+        e.mode = E_RGB;
+        e.o0 = B.rgb;
+        e.ld0 = 4;
+        e.o1 = B.dz;
+        e.ld1 = 4;
+        e.bias = Wc + F->cb_off[nc];
+        e.S = (int)S;
+        e.drgb = d_rgb;
+        BWD(gemm_row(C, R, 3, W, B.Hc[nc - 1], W, B.Cn[nc], cldn(nc), e));
     }
-    // dW_c4 += dz^T H3 ; db += sum dz ; dH3 = dz W_c4
-    BLAS(gemm_rm(G, true, false, 3, W, R, 1.0f, B.T0, 3, B.Hc[nc - 1], W, 1.0f, gc + F->cw_off[nc], W));
-    BLAS(colsum(st, R, 3, B.T0, 3, B.part, gc + F->cb_off[nc]));
-    BLAS(gemm_rm(G, false, false, R, W, 3, 1.0f, B.T0, 3, Wc + F->cw_off[nc], W, 0.0f, B.T1, W));
+    // ---- colour backward: dW_out += dz^T H ; db += sum dz ; dZ = (dz W_out) [H > 0]
+    BWD(gemm_wgrad(C, R, 3, W, B.dz, 4, B.Hc[nc - 1], W, gc + F->cw_off[nc], W,
+                   gc + F->cb_off[nc]));
+    {
+        Epi e;
+        e.mode = E_MASK;
+        e.o0 = B.T1;
+        e.ld0 = W;
+        e.i0 = B.Hc[nc - 1];
+        e.ldi0 = W;
+        BWD(gemm_row(C, R, W, 3, B.dz, 4, B.Ct[nc], cldt(nc), e));
+    }
+    float *dZ = B.T1, *dZn = B.T2;
     for (int l = nc - 1; l >= 0; --l) {
         const int in = F->cdin[l];
-        float *dH = B.T1, *dZ = B.T2;
-        const float *Z = B.Zc[l];
-        map((int64_t)R * W, st, [=] __device__(int64_t i) { dZ[i] = Z[i] > 0.0f ? dH[i] : 0.0f; });
         const float *X = l == 0 ? B.Cin : B.Hc[l - 1];
-        BLAS(gemm_rm(G, true, false, W, in, R, 1.0f, dZ, W, X, in, 1.0f, gc + F->cw_off[l], in));
-        BLAS(colsum(st, R, W, dZ, W, B.part, gc + F->cb_off[l]));
-        // dX = dZ W_c : [R, in] (into T1, ld = in)
-        BLAS(gemm_rm(G, false, false, R, in, W, 1.0f, dZ, W, Wc + F->cw_off[l], in, 0.0f, B.T1, in));
+        const int ldx = l == 0 ? ldc : W;
+        BWD(gemm_wgrad(C, R, W, in, dZ, W, X, ldx, gc + F->cw_off[l], in, gc + F->cb_off[l]));
+        Epi e;
+        if (l > 0) {
+            e.mode = E_MASK;
+            e.o0 = dZn;
+            e.ld0 = W;
+            e.i0 = B.Hc[l - 1];
+            e.ldi0 = W;
+        } else {
+            e.o0 = dZn;   // d Cin [R, cin] (ld ldc)
+            e.ld0 = ldc;
+        }
+        BWD(gemm_row(C, R, in, W, dZ, W, B.Ct[l], cldt(l), e));
+        float *tmp = dZ;
+        dZ = dZn;
+        dZn = tmp;
     }
-    // B.T1 now holds d Cin [R, cin]
-    // ---- g_bar = d grad (samples) + d Cin[:, 6:9] ; eikonal rows; encoding-space g_bar
+    const float *dCin = dZ;   // [R, cin], ld ldc
+    // ---- g_bar = d grad (samples) + d Cin[:, 6:9] ; eikonal rows
+    // 2 lambda (|g| - 1) g / |g| / P ; encoding-space g_bar = J g_bar[axis]
     {
-        float *gbar = B.gbar, *gbg = B.gbar_g, *loss = B.loss;
-        const float *dC = B.T1, *g = B.g, *J = B.J;
+        float *gbg = B.gbar_g, *eik = B.eik;
+        const float *g = B.g, *J = B.J;
         const int Si = (int)S;
         const float lam = P > 0 ? eik_lambda / (float)P : 0.0f;
-        map((int64_t)R, st, [=] __device__(int64_t r) {
-            float gb3[3];
+        map2(R, dg, st, [=] __device__(int r, int j) {
+            const int a = gamma_axis(j);
+            float gb;
             if (r < Si) {
-                for (int a = 0; a < 3; ++a)
-                    gb3[a] = (d_grad ? d_grad[3 * r + a] : 0.0f) + dC[r * cin + 6 + a];
+                gb = (d_grad ? d_grad[3 * r + a] : 0.0f) + dCin[(unsigned)(r * ldc + 6 + a)];
             } else {
-                float gx = g[3 * r], gy = g[3 * r + 1], gz = g[3 * r + 2];
-                float n = sqrtf(gx * gx + gy * gy + gz * gz);
-                float k = n > 0.0f ? 2.0f * lam * (n - 1.0f) / n : 0.0f;
-                gb3[0] = k * gx;
-                gb3[1] = k * gy;
-                gb3[2] = k * gz;
-                atomicAdd(loss, lam * (n - 1.0f) * (n - 1.0f));
+                const float gx = g[3 * r], gy = g[3 * r + 1], gz = g[3 * r + 2];
+                const float n = sqrtf(gx * gx + gy * gy + gz * gz);
+                const float k = n > 0.0f ? 2.0f * lam * (n - 1.0f) / n : 0.0f;
+                gb = k * g[3 * r + a];
             }
-            for (int a = 0; a < 3; ++a) gbar[3 * r + a] = gb3[a];
-            for (int j = 0; j < dg; ++j) gbg[r * dg + j] = J[r * dg + j] * gb3[gamma_axis(j)];
+            gbg[(unsigned)(r * ldg + j)] = J[(unsigned)(r * ldg + j)] * gb;
+        });
+        const float *gg = B.g;
+        map(P, st, [=] __device__(int64_t k) {
+            const int64_t r = Si + k;
+            const float gx = gg[3 * r], gy = gg[3 * r + 1], gz = gg[3 * r + 2];
+            const float n = sqrtf(gx * gx + gy * gy + gz * gz);
+            eik[k] = lam * (n - 1.0f) * (n - 1.0f);
         });
     }
     {
         float *Yb = B.Ybar;
-        const float *dC = B.T1;
         const int Si = (int)S;
-        map((int64_t)R * ny, st, [=] __device__(int64_t i) {
-            int64_t r = i / ny;
-            int j = (int)(i - r * ny);
+        map2(R, ny, st, [=] __device__(int r, int j) {
             float y = 0.0f;
-            if (r < Si) y = j == 0 ? (d_f ? scale * d_f[r] : 0.0f) : dC[r * cin + 9 + (j - 1)];
-            Yb[i] = y;
+            if (r < Si) y = j == 0 ? (d_f ? scale * d_f[r] : 0.0f) : dCin[(size_t)r * ldc + 9 + (j - 1)];
+            Yb[(size_t)r * ldy + j] = y;
         });
     }
-    // ---- second-order pass (adjoint of the reverse pass), forward in l
-    // delta_bar_0 = gbar_g W_0^T ; dW_0 += delta_0^T gbar_g
-    BLAS(gemm_rm(G, false, true, R, F->dout[0], dg, 1.0f, B.gbar_g, dg, Wl(0), dg, 0.0f, B.T0, W));
-    BLAS(gemm_rm(G, true, false, F->dout[0], dg, R, 1.0f, B.D[0], W, B.gbar_g, dg, 1.0f, gW(0), dg));
+    // ---- second-order pass (adjoint of the reverse pass), forward in l:
+    // delta_bar_0 = gbar_g W_0^T, then per layer E_bar_l = delta_bar sp,
+    // Z2_l = delta_bar E_l sp' (E = w_f on the last layer), delta_bar_{l+1} =
+    // E_bar'_l W_{l+1}^T and dW_{l+1} += delta_{l+1}^T E_bar'_l
+    auto so_epi = [&](int l, float *Eb) {
+        Epi e;
+        e.mode = E_SO;
+        e.o0 = Eb;
+        e.ld0 = W;
+        e.o1 = B.Z2[l];
+        e.ld1 = W;
+        e.i0 = B.Z[l];
+        e.ldi0 = W;
+        if (l == nh - 1) {
+            e.bias = wf;
+        } else {
+            e.i1 = B.E[l];
+            e.ldi1 = W;
+        }
+        e.beta = beta;
+        return e;
+    };
+    float *Eb = B.T0, *Ebn = B.T1;
+    BWD(gemm_row(C, R, F->dout[0], dg, B.gbar_g, ldg, B.Wn[0], ldn(0), so_epi(0, Eb)));
+    BWD(gemm_wgrad(C, R, F->dout[0], dg, B.D[0], W, B.gbar_g, ldg, gW(0), dg));
     for (int l = 0; l < nh; ++l) {
-        // B.T0 holds delta_bar_l [R, dout[l]]
         const int out = F->dout[l];
-        float *Eb = B.T1, *Z2 = B.Z2[l];
-        const float *db = B.T0, *Z = B.Z[l];
-        const bool top = (l == nh - 1);
-        const float *E = top ? Wl(nh) : B.E[l];   // top: w_f broadcast over rows
-        map((int64_t)R * out, st, [=] __device__(int64_t i) {
-            int64_t r = i / out;
-            int j = (int)(i - r * out);
-            float z = Z[r * W + j];
-            float sp = sig(beta * z);
-            float spp = beta * sp * (1.0f - sp);
-            float e = top ? E[j] : E[r * W + j];
-            float dbv = db[r * W + j];
-            Eb[r * W + j] = dbv * sp;          // E_bar_l (top: summed into w_f)
-            Z2[r * W + j] = dbv * e * spp;
-        });
-        if (top) {
+        if (l == nh - 1) {
             // w_f_bar += column sums of delta_bar * softplus'(z)
-            BLAS(colsum(st, R, out, B.T1, W, B.part, gW(nh)));
+            BWD(colsum(st, R, out, Eb, W, B.part, gW(nh)));
             break;
         }
         const int ln = l + 1;
         const int inn = F->din[ln], outn = F->dout[ln];
+        const float *A = Eb;
         if (ln == skip) {
             // E_bar'_l = [E_bar_l / sqrt2 | gbar_g / sqrt2]
             float *Ep = B.T2;
-            const float *gbg = B.gbar_g;
-            map((int64_t)R * inn, st, [=] __device__(int64_t i) {
-                int64_t r = i / inn;
-                int j = (int)(i - r * inn);
-                Ep[r * W + j] = rs2 * (j < out ? Eb[r * W + j] : gbg[r * dg + (j - out)]);
+            const float *Ebl = Eb, *gbg = B.gbar_g;
+            map2(R, inn, st, [=] __device__(int r, int j) {
+                Ep[(size_t)r * W + j] =
+                    rs2 * (j < out ? Ebl[(size_t)r * W + j] : gbg[(size_t)r * ldg + (j - out)]);
             });
-            BLAS(gemm_rm(G, false, true, R, outn, inn, 1.0f, B.T2, W, Wl(ln), inn, 0.0f, B.T0, W));
-            BLAS(gemm_rm(G, true, false, outn, inn, R, 1.0f, B.D[ln], W, B.T2, W, 1.0f, gW(ln), inn));
-        } else {
-            BLAS(gemm_rm(G, false, true, R, outn, inn, 1.0f, B.T1, W, Wl(ln), inn, 0.0f, B.T0, W));
-            BLAS(gemm_rm(G, true, false, outn, inn, R, 1.0f, B.D[ln], W, B.T1, W, 1.0f, gW(ln), inn));
+            A = Ep;
         }
+        BWD(gemm_row(C, R, outn, inn, A, W, B.Wn[ln], ldn(ln), so_epi(ln, Ebn)));
+        BWD(gemm_wgrad(C, R, outn, inn, B.D[ln], W, A, W, gW(ln), inn));
+        float *tmp = Eb;
+        Eb = Ebn;
+        Ebn = tmp;
     }
     // ---- first-order pass (ordinary backprop of the forward, with the
-    // second-order contributions Z2 injected at every hidden layer)
-    BLAS(gemm_rm(G, true, false, ny, W, R, 1.0f, B.Ybar, ny, B.X[nh], W, 1.0f, gW(nh), W));
-    BLAS(colsum(st, R, ny, B.Ybar, ny, B.part, gb(nh)));
-    BLAS(gemm_rm(G, false, false, R, W, ny, 1.0f, B.Ybar, ny, Wl(nh), W, 0.0f, B.T0, W));
-    float hbar_scale = 1.0f;   // 1/sqrt2 when T0 came through the skip input
+    // second-order contributions Z2 injected at every hidden layer):
+    // Zbar_l = Hbar_l softplus'(Z_l) (x 1/sqrt2 out of the skip input) + Z2_l
+    BWD(gemm_wgrad(C, R, ny, W, B.Ybar, ldy, B.X[nh], W, gW(nh), W, gb(nh)));
+    auto fo_epi = [&](int l, float s0, float *Zb) {
+        Epi e;
+        e.mode = E_FO;
+        e.o0 = Zb;
+        e.ld0 = W;
+        e.s0 = s0;
+        e.split = F->dout[l];
+        e.i0 = B.Z[l];
+        e.ldi0 = W;
+        e.i1 = B.Z2[l];
+        e.ldi1 = W;
+        e.beta = beta;
+        return e;
+    };
+    float *Zb = B.T0, *Zbn = B.T1;
+    BWD(gemm_row(C, R, W, ny, B.Ybar, ldy, B.Wt[nh], ldt(nh), fo_epi(nh - 1, 1.0f, Zb)));
     for (int l = nh - 1; l >= 0; --l) {
         const int in = F->din[l], out = F->dout[l];
-        float *Zb = B.T1;
-        const float *Hb = B.T0, *Z = B.Z[l], *Z2 = B.Z2[l];
-        const float hsc = hbar_scale;
-        map((int64_t)R * out, st, [=] __device__(int64_t i) {
-            int64_t r = i / out;
-            int j = (int)(i - r * out);
-            Zb[r * W + j] = hsc * Hb[r * W + j] * sig(beta * Z[r * W + j]) + Z2[r * W + j];
-        });
-        BLAS(gemm_rm(G, true, false, out, in, R, 1.0f, B.T1, W, B.X[l], in, 1.0f, gW(l), in));
-        BLAS(colsum(st, R, out, B.T1, W, B.part, gb(l)));
+        BWD(gemm_wgrad(C, R, out, in, Zb, W, B.X[l], l == 0 ? ldg : W, gW(l), in, gb(l)));
         if (l > 0) {
-            BLAS(gemm_rm(G, false, false, R, in, out, 1.0f, B.T1, W, Wl(l), in, 0.0f, B.T0, W));
-            hbar_scale = (l == skip) ? rs2 : 1.0f;
+            BWD(gemm_row(C, R, in, out, Zb, W, B.Wt[l], ldt(l),
+                         fo_epi(l - 1, (l == skip) ? rs2 : 1.0f, Zbn)));
+            float *tmp = Zb;
+            Zb = Zbn;
+            Zbn = tmp;
         }
     }
     if (eik_loss_out) {
-        const float *loss = B.loss;
-        map(1, st, [=] __device__(int64_t) { *eik_loss_out = loss[0]; });
+        if (P > 0)
+            hipLaunchKernelGGL(k_sum_fixed, dim3(1), dim3(256), 0, st, B.eik, (int)P, eik_loss_out);
+        else
+            map(1, st, [=] __device__(int64_t) { *eik_loss_out = 0.0f; });
     }
+    TSDFS_LAUNCH_CHECK();
     return TSDFS_OK;
 }
 
@@ -714,7 +915,7 @@ int sdf_mlp_bwd_ws_bytes(const tsdfs_field *F, int64_t n_rows, size_t *bytes) {
     return TSDFS_OK;
 }
 
-int sdf_mlp_bwd(tsdfs_field *F, const float *o, const float *v, const float *t,
+int sdf_mlp_bwd(const tsdfs_field *F, const float *o, const float *v, const float *t,
                 const int32_t *ray_id, int64_t n_samples, const float *eik_x, int64_t n_eik,
                 float eik_lambda, const float *d_f, const float *d_grad_f, const float *d_rgb,
                 int32_t precision, float *d_params_sdf, float *d_params_color, float *eik_loss,
@@ -732,42 +933,11 @@ int sdf_mlp_bwd(tsdfs_field *F, const float *o, const float *v, const float *t,
     TSDFS_CHECK_ARG(n_eik == 0 || eik_x, "NULL eikonal points");
     size_t need;
     sdf_mlp_bwd_ws_bytes(F, n_samples + n_eik, &need);
-    TSDFS_CHECK_ARG(ws && ws_bytes >= need, "workspace too small (%zu < %zu)", ws_bytes, need);
-    int rc = network_backward(F, o, v, t, ray_id, n_samples, eik_x, n_eik, eik_lambda, d_f,
-                              d_grad_f, d_rgb, d_params_sdf, d_params_color, (char *)ws,
-                              as_stream(stream), eik_loss, precision == TSDFS_BF16);
-    if (rc) return rc;
-    TSDFS_LAUNCH_CHECK();
-    return TSDFS_OK;
-}
-
-int composite_bwd(const int32_t *offsets, int64_t n_rays, const float *v, const float *dt,
-                  const float *f, const float *grad_f, const float *rgb, float s,
-                  const float *d_out_rgb, float *d_f, float *d_grad_f, float *d_rgb,
-                  void *stream) {
-    TSDFS_CHECK_ARG(n_rays >= 0 && s > 0.0f, "bad arguments");
-    if (n_rays == 0) return TSDFS_OK;
-    TSDFS_CHECK_ARG(offsets && v && dt && f && grad_f && rgb && d_out_rgb && d_f && d_grad_f && d_rgb,
-                    "NULL array argument");
-    hipLaunchKernelGGL(k_composite_bwd, dim3((unsigned)((n_rays + 255) / 256)), dim3(256), 0,
-                       as_stream(stream), offsets, n_rays, v, dt, f, grad_f, rgb, s, d_out_rgb,
-                       d_f, d_grad_f, d_rgb);
-    TSDFS_LAUNCH_CHECK();
-    return TSDFS_OK;
-}
-
-int rgb_loss(const float *rgb, const float *target, int64_t n_rays, float *d_rgb, float *loss,
-             void *stream) {
-    TSDFS_CHECK_ARG(n_rays >= 0, "bad arguments");
-    TSDFS_CHECK_ARG(loss != nullptr, "NULL loss");
-    hipStream_t st = as_stream(stream);
-    map(1, st, [=] __device__(int64_t) { *loss = 0.0f; });
-    if (n_rays == 0) return TSDFS_OK;
-    TSDFS_CHECK_ARG(rgb && target && d_rgb, "NULL array argument");
-    hipLaunchKernelGGL(k_rgb_loss, dim3((unsigned)((n_rays + 255) / 256)), dim3(256), 0, st, rgb,
-                       target, n_rays, d_rgb, loss);
-    TSDFS_LAUNCH_CHECK();
-    return TSDFS_OK;
+    TSDFS_CHECK_ARG(ws && ws_bytes >= need && (uintptr_t)ws % 256 == 0,
+                    "workspace too small or not 256-byte aligned (%zu < %zu)", ws_bytes, need);
+    return network_backward(F, o, v, t, ray_id, n_samples, eik_x, n_eik, eik_lambda, d_f,
+                            d_grad_f, d_rgb, d_params_sdf, d_params_color, (char *)ws,
+                            as_stream(stream), eik_loss, precision == TSDFS_BF16);
 }
 
 // Adam (the optimiser of the NeuS-family training the paper builds on):

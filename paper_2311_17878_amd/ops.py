@@ -173,14 +173,13 @@ def place(bounds, rho_num, rho_den, n_min, n_max, s_cap=None, sync=True, ws=None
     dt = torch.empty(max(s_cap, 1), dtype=torch.float32, device=d)
     ray_id = torch.empty(max(s_cap, 1), dtype=torch.int32, device=d)
     s_total = torch.zeros(1, dtype=torch.int64, device=d)
+    host_total = ctypes.c_int64(-1)
+    args = (_p(bounds["t_n"]), _p(bounds["t_f"]), _p(bounds["n_vox"]), _p(bounds["status"]), R,
+            rho_num, rho_den, n_min, n_max, _p(counts), _p(offsets), _p(t), _p(dt), _p(ray_id),
+            s_cap, _p(s_total), ctypes.byref(host_total) if sync else None)
     if ws is None:
         ws = torch.empty(max(place_ws_bytes(R), 8), dtype=torch.uint8, device=d)
-    host_total = ctypes.c_int64(-1)
-    L.check(L.load().place_samples(_p(bounds["t_n"]), _p(bounds["t_f"]), _p(bounds["n_vox"]),
-                                   _p(bounds["status"]), R, rho_num, rho_den, n_min, n_max,
-                                   _p(counts), _p(offsets), _p(t), _p(dt), _p(ray_id), s_cap,
-                                   _p(s_total), ctypes.byref(host_total) if sync else None,
-                                   _p(ws), ws.numel(), _stream()))
+    L.check(L.load().place_samples(*args, _p(ws), ws.numel(), _stream()))
     out = dict(counts=counts, offsets=offsets, t=t, dt=dt, ray_id=ray_id, s_total=s_total)
     if sync:
         S = host_total.value
@@ -415,15 +414,19 @@ def composite(offsets, v, t, dt, f, grad, rgb, s, want_w=False):
     return out
 
 
-def composite_bwd(offsets, v, dt, f, grad, rgb, s, d_out_rgb):
+def composite_bwd(offsets, v, t, dt, f, grad, rgb, s, d_out_rgb=None, d_out_depth=None,
+                  d_out_normal=None, d_out_acc=None):
+    """Per-sample adjoints (d_f, d_grad_f, d_rgb) of composite() from the
+    per-ray adjoints of its outputs (None = zero)."""
     S = f.shape[0]
     d = _dev()
     d_f = torch.empty(max(S, 1), dtype=torch.float32, device=d)
     d_g = torch.empty((max(S, 1), 3), dtype=torch.float32, device=d)
     d_c = torch.empty((max(S, 1), 3), dtype=torch.float32, device=d)
-    L.check(L.load().composite_bwd(_p(offsets), offsets.shape[0] - 1, _p(v), _p(dt), _p(f),
-                                   _p(grad), _p(rgb), float(s), _p(d_out_rgb), _p(d_f), _p(d_g),
-                                   _p(d_c), _stream()))
+    L.check(L.load().composite_bwd(_p(offsets), offsets.shape[0] - 1, _p(v), _p(t), _p(dt), _p(f),
+                                   _p(grad), _p(rgb), float(s), _p(d_out_rgb), _p(d_out_depth),
+                                   _p(d_out_normal), _p(d_out_acc), _p(d_f), _p(d_g), _p(d_c),
+                                   _stream()))
     return d_f[:S], d_g[:S], d_c[:S]
 
 
