@@ -1,15 +1,30 @@
-"""GPU parity on the large panorama workload (12x8x3 m, 512^3 TSDF,
-equirectangular 2048x1024 view, BF16 field): the full-size grid with the
-training rays of two views (so that the oracle finishes in seconds), bounds
-of 4096 seeded panorama rays bit-exact, and the BF16 field's error stated."""
+"""GPU parity on the large panorama workload (12x8x3 m, 512^3 TSDF fused from
+all 300 training views of 512^2, equirectangular 2048x1024 view):
+
+* the fused volume's flags bit-exact against the oracle's (stored by
+  tests/golden/make_volume_golden.py from the oracle alone), counts and V at
+  200 000 seeded voxels, and the total number of voxel updates;
+* bounds (t_n, t_f, first_hit, n_vox, status, steps) and the adaptive
+  placement of 65 536 seeded panorama rays bit-exact against the oracle's
+  Alg. 1 on those flags;
+* the rendered depth, colour and weight sum of 256 seeded rays against the
+  oracle's field and compositing, in FP32 (depth within 1e-3 h) and in
+  BF16 (errors stated in units of the voxel size h, bounded from the
+  measured values).
+"""
+import os
+
 import numpy as np
 import pytest
 import torch
 
 from synth.configs import get_config
-from oracle import tsdf as OT, field as OF
+from oracle import tsdf as OT, field as OF, render as OR
 
 pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "c5_volume.npz")
+EPS32 = np.float64(np.finfo(np.float32).eps)
 
 
 def dev(a):
@@ -23,61 +38,142 @@ def host(t):
 @pytest.fixture(scope="module")
 def c5():
     from paper_2311_17878_amd import ops
+    from paper_2311_17878_amd.pipeline import TsdfRenderer
     cfg = get_config("c5")
-    g = cfg.grid
-    o, v, d = cfg.integration_rays(views=[0, 1])
+    g, s = cfg.grid, cfg.sampling
+    print("C5: depth maps of 300 views ...", flush=True)
+    o, v, d = cfg.integration_rays()
     grid = ops.make_grid(g.n, g.lo, g.h, g.d_t, g.d_s, g.nb_radius, g.m_consec)
-    st = ops.new_state(grid)
+    field = ops.Field(cfg.sdf.width, cfg.sdf.n_hidden, cfg.sdf.pe_freqs, cfg.sdf.skip_at,
+                      cfg.sdf.n_feat, cfg.color.n_hidden, cfg.sdf.beta, cfg.in_center,
+                      cfg.in_scale, cfg.sdf_params(), cfg.color_params())
+    R = TsdfRenderer(grid, field, s.rho_num, s.rho_den, s.n_min, s.n_max, cfg.neus_s)
     nup = torch.zeros(1, dtype=torch.int64, device="cuda")
-    ops.integrate(grid, st, dev(o), dev(v), dev(d), nup)
-    V, fl = ops.finalize(grid, st)
-    ost = OT.integrate(g, o, v, d, tie_eps=2.0 ** -36)
-    oV = OT.finalize(g, ost)
-    ofl = OT.flags(g, oV)
+    print("C5: integrating %d rays on the GPU" % o.shape[0], flush=True)
+    R.integrate(dev(o), dev(v), dev(d), n_updates=nup, batch=1 << 24)
+    del o, v, d
+    V, _ = R.finalize(want_v=True)
+    torch.cuda.synchronize()
+    gold = np.load(GOLDEN)
+    N = int(gold["n_vox"])
+    ofl = (np.unpackbits(gold["flag0"])[:N] | (np.unpackbits(gold["flag1"])[:N] << 1)).astype(np.uint8)
     ro, rv = cfg.render_rays()
-    pick = np.sort(np.random.default_rng(0).choice(ro.shape[0], 4096, replace=False))
-    return dict(cfg=cfg, g=g, grid=grid, st=st, V=V, fl=fl, nup=nup, ost=ost, oV=oV, ofl=ofl,
+    pick = np.sort(np.random.default_rng(0).choice(ro.shape[0], 65536, replace=False))
+    return dict(cfg=cfg, g=g, grid=grid, R=R, V=V, nup=nup, gold=gold, ofl=ofl,
                 ro=ro[pick], rv=rv[pick])
 
 
-def test_volume_full_grid(c5):
+def test_volume_from_all_views(c5):
+    """Flags of the 512^3 volume bit-exact; counts exact and V within
+    1e-5 D_T at the stored voxels; the update total equal."""
     from paper_2311_17878_amd import ops
-    g = c5["g"]
-    assert c5["ost"].ties == 0
-    assert int(c5["nup"].item()) == c5["ost"].updates
-    _, cnt = ops.state_views(c5["grid"], c5["st"])
-    assert np.array_equal(host(cnt).astype(np.int64), c5["ost"].cnt)
-    assert np.abs(host(c5["V"]) - c5["oV"].ravel()).max() <= 1e-5 * float(np.float32(g.d_t))
-    assert np.array_equal(host(c5["fl"]), c5["ofl"].ravel())
+    gold, g = c5["gold"], c5["g"]
+    assert int(gold["ties"]) == 0
+    assert int(c5["nup"].item()) == int(gold["updates"])
+    fl = host(c5["R"].flags)
+    assert np.array_equal(fl, c5["ofl"])
+    idx = gold["sample_idx"]
+    _, cnt = ops.state_views(c5["grid"], c5["R"].state)
+    assert np.array_equal(host(cnt)[idx].astype(np.int64), gold["sample_cnt"])
+    assert np.abs(host(c5["V"])[idx] - gold["sample_V"]).max() <= 1e-5 * float(np.float32(g.d_t))
+    n0, n1 = int((fl & 1).sum()), int((fl >> 1).sum())
+    print("C5 volume: %d updates; flag0 %d, flag1 %d of %d voxels" %
+          (int(gold["updates"]), n0, n1, fl.size))
 
 
-def test_panorama_bounds_and_bf16_field(c5):
-    from paper_2311_17878_amd import ops, _lib as L
+def test_panorama_bounds_and_placement(c5):
+    """Alg. 1 bounds and the adaptive placement of 65 536 panorama rays
+    bit-exact (sample positions within two roundings)."""
+    from paper_2311_17878_amd import ops
     cfg, g = c5["cfg"], c5["g"]
+    s = cfg.sampling
     ro, rv = c5["ro"], c5["rv"]
     ob = OT.bounds(g, c5["ofl"], ro, rv)
-    gb = ops.ray_bounds(c5["grid"], c5["fl"], dev(ro), dev(rv), steps=True)
+    gb = ops.ray_bounds(c5["grid"], c5["R"].flags, dev(ro), dev(rv), steps=True)
     for k in ("t_n", "t_f", "first_hit", "n_vox", "status", "n_steps"):
         assert np.array_equal(host(gb[k]), ob[k]), k
-    s = cfg.sampling
-    op = OT.place(ob["t_n"], ob["t_f"], ob["n_vox"], ob["status"], s.rho_num, s.rho_den, s.n_min, s.n_max)
-    gp = ops.place(gb, s.rho_num, s.rho_den, s.n_min, s.n_max)
+    st = np.bincount(ob["status"], minlength=4)
+    op = OT.place(ob["t_n"], ob["t_f"], ob["n_vox"], ob["status"], s.rho_num, s.rho_den, s.n_min,
+                  s.n_max)
+    gp = ops.place(gb, s.rho_num, s.rho_den, s.n_min, s.n_max, sync=True)
     assert np.array_equal(host(gp["counts"]), op["counts"])
-    counts = op["counts"]
-    print("C5 panorama (2 views fused): status", np.bincount(ob["status"], minlength=4),
-          "samples/ray min %d max %d mean %.2f" % (counts.min(), counts.max(), counts.mean()))
-    F = ops.Field(cfg.sdf.width, cfg.sdf.n_hidden, cfg.sdf.pe_freqs, cfg.sdf.skip_at, cfg.sdf.n_feat,
-                  cfg.color.n_hidden, cfg.sdf.beta, cfg.in_center, cfg.in_scale, cfg.sdf_params(),
-                  cfg.color_params())
-    t32 = op["t"].astype(np.float32)
-    rid = op["ray_id"].astype(np.int32)
-    f, gr, rgb = F.forward(dev(ro), dev(rv), dev(t32), dev(rid), precision=L.BF16)
-    torch.cuda.synchronize()
-    sel = np.sort(np.random.default_rng(1).choice(t32.size, min(1024, t32.size), replace=False))
-    of, og, orgb = OF.eval_samples(cfg, cfg.sdf_params(), cfg.color_params(), ro, rv, t32[sel], rid[sel])
-    ef = np.abs(host(f)[sel] - of)
-    eg = np.linalg.norm(host(gr)[sel] - og, axis=1) / np.maximum(np.linalg.norm(og, axis=1), 1e-6)
-    ec = np.abs(host(rgb)[sel] - orgb)
-    print("BF16 C5: f abs err max %.3g mean %.3g | grad rel err mean %.3g | rgb max %.3g"
-          % (ef.max(), ef.mean(), eg.mean(), ec.max()))
-    assert ef.max() <= 0.1 and eg.mean() <= 5e-2 and ec.max() <= 5e-2
+    assert np.array_equal(host(gp["offsets"]), op["offsets"])
+    S = int(op["offsets"][-1])
+    assert gp["S"] == S
+    assert np.array_equal(host(gp["ray_id"])[:S], op["ray_id"])
+    tf = np.abs(ob["t_f"][op["ray_id"]]).astype(np.float64)
+    assert (np.abs(host(gp["t"])[:S] - op["t"]) <= 8 * EPS32 * tf).all()
+    c = op["counts"][ob["status"] <= 1]
+    print("C5 panorama, 65536 rays: status HIT/NO_FAR/MISS/INVALID", st.tolist(),
+          "| steps per ray mean %.1f max %d" % (ob["n_steps"].mean(), ob["n_steps"].max()),
+          "| samples/ray min %d p50 %d p99 %d max %d mean %.2f" %
+          (c.min(), np.median(c), np.percentile(c, 99), c.max(), op["counts"].mean()))
+    # inside the closed rooms every ray finds both bounds; the bounds have
+    # many lengths, from the M = 15 voxel minimum to past the n_max cap
+    assert st[0] > 0 and st[3] == 0
+    assert len(np.unique(c)) >= 20 and c.max() == s.n_max
+    assert ob["n_steps"].max() > 4 * ob["n_steps"].min()
+
+
+def _oracle_render(c5, rays):
+    cfg, g = c5["cfg"], c5["g"]
+    s = cfg.sampling
+    ro, rv = c5["ro"][rays], c5["rv"][rays]
+    ob = OT.bounds(g, c5["ofl"], ro, rv)
+    op = OT.place(ob["t_n"], ob["t_f"], ob["n_vox"], ob["status"], s.rho_num, s.rho_den, s.n_min,
+                  s.n_max)
+    f, gr, rgb = OF.eval_samples(cfg, cfg.sdf_params(), cfg.color_params(), ro, rv, op["t"],
+                                 op["ray_id"])
+    return OR.composite(op["offsets"], rv, op["t"], op["dt"], f, gr, rgb, cfg.neus_s)
+
+
+@pytest.fixture(scope="module")
+def c5_render(c5):
+    from paper_2311_17878_amd import _lib as L
+    rays = np.sort(np.random.default_rng(1).choice(c5["ro"].shape[0], 256, replace=False))
+    ref = _oracle_render(c5, rays)
+    R = c5["R"]
+    outs = {}
+    for name, prec in (("fp32", L.FP32), ("bf16", L.BF16)):
+        R.precision = prec
+        try:
+            out = R.render(dev(c5["ro"]), dev(c5["rv"]))
+        finally:
+            R.precision = L.FP32
+        outs[name] = {k: host(out[k]) for k in ("rgb", "depth", "normal", "acc")}
+    return rays, ref, outs
+
+
+def _errors(c5, rays, ref, out):
+    h = float(c5["g"].h)
+    big = ref["acc"] > 1e-2
+    ed = np.abs(out["depth"][rays][big] - ref["depth"][big]) / h
+    ec = np.abs(out["rgb"][rays] - ref["rgb"])
+    ea = np.abs(out["acc"][rays] - ref["acc"])
+    return big, ed, ec, ea
+
+
+def test_panorama_render_fp32(c5, c5_render):
+    rays, ref, outs = c5_render
+    big, ed, ec, ea = _errors(c5, rays, ref, outs["fp32"])
+    print("C5 FP32 vs oracle on 256 rays (%d with acc > 1%%): depth err max %.3g h, "
+          "p99 %.3g h | rgb max %.3g | acc max %.3g" %
+          (big.sum(), ed.max(), np.percentile(ed, 99), ec.max(), ea.max()))
+    assert big.sum() > 64
+    assert ed.max() <= 1e-3 and ec.max() <= 1e-4 and ea.max() <= 1e-4
+
+
+def test_panorama_render_bf16(c5, c5_render):
+    """BF16 products (FP32 accumulation): error against the FP64 oracle in
+    units of h, and PSNR of the BF16 image against the FP32 image."""
+    rays, ref, outs = c5_render
+    big, ed, ec, ea = _errors(c5, rays, ref, outs["bf16"])
+    mse = float(((outs["bf16"]["rgb"] - outs["fp32"]["rgb"]) ** 2).mean())
+    psnr = 10 * np.log10(1.0 / max(mse, 1e-30))
+    print("C5 BF16 vs oracle on 256 rays: depth err max %.3g h, p99 %.3g h, mean %.3g h | "
+          "rgb max %.3g | acc max %.3g | PSNR BF16 vs FP32 (65536 rays) %.1f dB" %
+          (ed.max(), np.percentile(ed, 99), ed.mean(), ec.max(), ea.max(), psnr))
+    # measured: depth max 0.167 h, p99 0.129 h; rgb 0.019; acc 0.036; 55 dB
+    assert ed.max() <= 0.25 and np.percentile(ed, 99) <= 0.2
+    assert ec.max() <= 0.03 and ea.max() <= 0.06
+    assert psnr >= 50.0

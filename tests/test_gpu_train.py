@@ -45,7 +45,11 @@ def c1_volume():
     return cfg, fl, (o, v, d)
 
 
-def test_composite_bwd_matches_oracle(c1_volume):
+@pytest.mark.parametrize("outputs", ["rgb", "depth", "normal", "acc", "all"])
+def test_composite_bwd_matches_oracle(c1_volume, outputs):
+    """Adjoint of the compositing (Eq. 1 colour, Eq. 2 depth, the rendered
+    normal and the weight sum) against FP64 reverse mode through the
+    oracle's compositing, one output at a time and all four together."""
     from paper_2311_17878_amd import ops
     cfg, fl, _ = c1_volume
     ro, rv = cfg.render_rays()
@@ -53,23 +57,32 @@ def test_composite_bwd_matches_oracle(c1_volume):
     s = cfg.sampling
     p = OT.place(b["t_n"], b["t_f"], b["n_vox"], b["status"], s.rho_num, s.rho_den, s.n_min, s.n_max)
     rng = np.random.default_rng(3)
-    S = p["t"].size
+    S, R = p["t"].size, ro.shape[0]
     f = rng.normal(0, 0.03, S).astype(np.float32)
     gr = rng.normal(0, 1, (S, 3)).astype(np.float32)
+    gr[::97] = 0.0                                  # samples with a zero gradient
     rgb = rng.uniform(0, 1, (S, 3)).astype(np.float32)
-    dC = rng.normal(0, 1, (ro.shape[0], 3)).astype(np.float32)
+    want = ("rgb", "depth", "normal", "acc") if outputs == "all" else (outputs,)
+    shapes = dict(rgb=(R, 3), depth=(R,), normal=(R, 3), acc=(R,))
+    up = {k: rng.normal(0, 1, shapes[k]).astype(np.float32) for k in want}
     t32, dt32 = p["t"].astype(np.float32), p["dt"].astype(np.float32)
     T = lambda a: torch.tensor(np.asarray(a, np.float64), requires_grad=True)
     ft, gt, ct = T(f), T(gr), T(rgb)
     out = OR.composite_t(p["offsets"], rv, torch.tensor(t32.astype(np.float64)),
                          torch.tensor(dt32.astype(np.float64)), ft, gt, ct, cfg.neus_s)
-    (out["rgb"] * torch.tensor(dC.astype(np.float64))).sum().backward()
-    df, dg, dc = ops.composite_bwd(dev(p["offsets"].astype(np.int32)), dev(rv), dev(dt32), dev(f),
-                                   dev(gr), dev(rgb), cfg.neus_s, dev(dC))
-    for name, a, bref in (("d_f", df, ft.grad), ("d_grad", dg, gt.grad), ("d_rgb", dc, ct.grad)):
-        e = np.abs(host(a) - bref.numpy()).max()
-        scale = np.abs(bref.numpy()).max()
-        print(name, "max abs err", e, "max |ref|", scale)
+    scalar = sum((out[k] * torch.tensor(up[k].astype(np.float64))).sum() for k in want)
+    scalar.backward()
+    args = {f"d_out_{k}": dev(up[k]) for k in want}
+    df, dg, dc = ops.composite_bwd(dev(p["offsets"].astype(np.int32)), dev(rv), dev(t32), dev(dt32),
+                                   dev(f), dev(gr), dev(rgb), cfg.neus_s, **args)
+    acc = out["acc"].detach().numpy()
+    print(outputs, "rays with acc > 0:", int((acc > 0).sum()), "min acc there %.3g" % acc[acc > 0].min())
+    for name, a, leaf in (("d_f", df, ft), ("d_grad", dg, gt), ("d_rgb", dc, ct)):
+        # an input that no requested output depends on has no gradient: zero
+        ref = leaf.grad.numpy() if leaf.grad is not None else np.zeros(leaf.shape)
+        e = np.abs(host(a) - ref).max()
+        scale = np.abs(ref).max()
+        print(outputs, name, "max abs err %.3g" % e, "max |ref| %.3g" % scale)
         assert e <= 1e-4 * max(scale, 1.0), name
 
 
@@ -126,31 +139,24 @@ def _train_batch(cfg, n_rays, n_eik, seed):
     return ro, rv, target, cfg.eikonal_points(n_eik, seed)
 
 
-@pytest.mark.parametrize("name,n_rays,n_eik,prec", [("c1", 96, 64, "fp32"), ("c2", 64, 64, "fp32"),
-                                                   ("c1", 96, 64, "bf16"), ("c2", 64, 64, "bf16")])
-def test_train_step_matches_oracle_and_fd(name, n_rays, n_eik, prec):
-    """One TSDF-bounded training step against the FP64 oracle's loss and
-    gradients, and against central differences of the oracle loss on 32
-    seeded weights (h = 1e-4, and h = 1e-6 for FP32).  BF16: every product
-    takes BF16-rounded inputs (forward and backward); the error is stated."""
-    from paper_2311_17878_amd import ops, _lib as L
+_RENDERERS = {}
+
+
+def _renderer(name):
+    """A renderer holding the workload's fused volume (GPU), and the oracle's
+    flags of the same volume (bit-exact with the GPU's, checked here)."""
+    if name in _RENDERERS:
+        return _RENDERERS[name]
+    from paper_2311_17878_amd import ops
     from paper_2311_17878_amd.pipeline import TsdfRenderer
-    from paper_2311_17878_amd.autograd import train_step
     cfg = get_config(name)
     g, s = cfg.grid, cfg.sampling
-    precision = L.BF16 if prec == "bf16" else L.FP32
     o, v, d = cfg.integration_rays()
     grid = ops.make_grid(g.n, g.lo, g.h, g.d_t, g.d_s, g.nb_radius, g.m_consec)
     F = make_field(cfg)
     R = TsdfRenderer(grid, F, s.rho_num, s.rho_den, s.n_min, s.n_max, cfg.neus_s)
     R.integrate(dev(o), dev(v), dev(d), batch=1 << 24)
     R.finalize(want_v=False)
-    ro, rv, target, eik = _train_batch(cfg, n_rays, n_eik, seed=7)
-    loss, leik, gs, gc, S = train_step(R, dev(ro), dev(rv), dev(target), dev(eik), eik_lambda=0.1,
-                                       precision=precision)
-    torch.cuda.synchronize()
-    # the oracle's own volume, bounds and placement for the same rays
-    fl = host(R.flags)      # bit-exact with the oracle's flags (checked in the parity suites)
     if name == "c1":
         st = OT.integrate(g, o, v, d)
         fl_o = OT.flags(g, OT.finalize(g, st)).ravel()
@@ -159,21 +165,47 @@ def test_train_step_matches_oracle_and_fd(name, n_rays, n_eik, prec):
         gold = np.load(os.path.join(os.path.dirname(__file__), "golden", "c2_volume.npz"))
         N = int(gold["n_vox"])
         fl_o = (np.unpackbits(gold["flag0"])[:N] | (np.unpackbits(gold["flag1"])[:N] << 1)).astype(np.uint8)
-    assert np.array_equal(fl, fl_o)
+    assert np.array_equal(host(R.flags), fl_o)
+    _RENDERERS[name] = (cfg, R, fl_o)
+    return _RENDERERS[name]
+
+
+def _oracle_step(cfg, fl_o, ro, rv, target, eik, lam=0.1):
+    g, s = cfg.grid, cfg.sampling
     b = OT.bounds(g, fl_o, ro, rv)
     p = OT.place(b["t_n"], b["t_f"], b["n_vox"], b["status"], s.rho_num, s.rho_den, s.n_min, s.n_max)
-    assert S == p["offsets"][-1]
     batch = dict(o=ro, v=rv, offsets=p["offsets"], t=p["t"], dt=p["dt"], target=target, eik_x=eik,
-                 eik_lambda=0.1)
+                 eik_lambda=lam)
     L_o, ref_s, ref_c = OTR.loss_and_grads(cfg, cfg.sdf_params(), cfg.color_params(), batch)
+    return p, batch, L_o, ref_s, ref_c
+
+
+@pytest.mark.parametrize("name,n_rays,n_eik,prec", [("c1", 96, 64, "fp32"), ("c2", 64, 64, "fp32"),
+                                                   ("c1", 96, 64, "bf16"), ("c2", 64, 64, "bf16")])
+def test_train_step_matches_oracle_and_fd(name, n_rays, n_eik, prec):
+    """One TSDF-bounded training step against the FP64 oracle's loss and
+    gradients, and against central differences of the oracle loss on 32
+    seeded weights (h = 1e-4, and h = 1e-6 for FP32).  BF16: every product
+    takes BF16-rounded inputs (forward and backward); the error is stated."""
+    from paper_2311_17878_amd import _lib as L
+    from paper_2311_17878_amd.autograd import train_step
+    cfg, R, fl_o = _renderer(name)
+    precision = L.BF16 if prec == "bf16" else L.FP32
+    ro, rv, target, eik = _train_batch(cfg, n_rays, n_eik, seed=7)
+    loss, leik, gs, gc, S = train_step(R, dev(ro), dev(rv), dev(target), dev(eik), eik_lambda=0.1,
+                                       precision=precision)
+    torch.cuda.synchronize()
+    # the oracle's bounds and placement for the same rays on its own flags
+    p, batch, L_o, ref_s, ref_c = _oracle_step(cfg, fl_o, ro, rv, target, eik)
+    assert S == p["offsets"][-1]
     got_L = float(loss.item() + leik.item())
     print(f"{name} {prec}: loss gpu {got_L:.9f} oracle {L_o:.9f}; samples {S}")
     cs, rs = compare(f"{name} {prec} sdf grads", host(gs), ref_s)
     cc, rc = compare(f"{name} {prec} colour grads", host(gc), ref_c)
     if prec == "fp32":
         assert abs(got_L - L_o) <= 1e-5 * max(1.0, abs(L_o))
-        assert cs >= 0.99999 and rs <= 1e-3
-        assert cc >= 0.99999 and rc <= 1e-3
+        assert cs >= 0.99999 and rs <= 1e-4
+        assert cc >= 0.99999 and rc <= 1e-4
     else:
         # BF16 rounding of both inputs of every product (forward recompute,
         # reverse pass, second-order terms, weight products): about 2^-8
@@ -211,6 +243,45 @@ def test_train_step_matches_oracle_and_fd(name, n_rays, n_eik, prec):
             assert rel <= 1e-3
         else:
             assert rel <= 0.1
+
+
+@pytest.mark.parametrize("prec,lam", [("fp32", 0.1), ("bf16", 0.1), ("bf16", 0.0)])
+def test_train_step_at_size(prec, lam):
+    """The training step of the room workload at a size where every
+    reduction over rows runs in several chunks (512 rays, about 9 k adaptive
+    samples, plus 8192 eikonal points: about 17 k rows, 34 weight-gradient
+    chunks of 512 rows and 17 bias-sum chunks of 1024), against the FP64
+    oracle's loss and gradients.  FP32: cosine >= 0.99999 and relative L2
+    <= 1e-4.  BF16: the error is stated; with the eikonal term it is larger
+    than without it, since the term's gradient is proportional to
+    |grad f| - 1 with |grad f| close to 1 under the geometric initialisation,
+    a difference that the BF16 rounding of grad f perturbs in relative
+    terms (measured: cosine 0.990, relative L2 0.16 with lambda = 0.1)."""
+    from paper_2311_17878_amd import _lib as L
+    from paper_2311_17878_amd.autograd import train_step
+    cfg, R, fl_o = _renderer("c2")
+    precision = L.BF16 if prec == "bf16" else L.FP32
+    ro, rv, target, eik = _train_batch(cfg, 512, 8192, seed=9)
+    loss, leik, gs, gc, S = train_step(R, dev(ro), dev(rv), dev(target), dev(eik), eik_lambda=lam,
+                                       precision=precision)
+    torch.cuda.synchronize()
+    p, batch, L_o, ref_s, ref_c = _oracle_step(cfg, fl_o, ro, rv, target, eik, lam)
+    assert S == p["offsets"][-1]
+    rows = S + eik.shape[0]
+    assert rows >= 4 * 2048 + 8192
+    got_L = float(loss.item() + leik.item())
+    print(f"c2 {prec} lambda {lam} at size: {S} samples + {eik.shape[0]} eikonal points = {rows} "
+          f"rows; loss gpu {got_L:.9f} oracle {L_o:.9f}")
+    cs, rs = compare(f"c2 {prec} lambda {lam} at size sdf grads", host(gs), ref_s)
+    cc, rc = compare(f"c2 {prec} lambda {lam} at size colour grads", host(gc), ref_c)
+    if prec == "fp32":
+        assert abs(got_L - L_o) <= 1e-5 * max(1.0, abs(L_o))
+        assert cs >= 0.99999 and rs <= 1e-4
+        assert cc >= 0.99999 and rc <= 1e-4
+    else:
+        assert abs(got_L - L_o) <= 2e-2 * max(1.0, abs(L_o))
+        assert cs >= 0.98 and rs <= 0.25
+        assert cc >= 0.999 and rc <= 0.02
 
 
 def test_backward_row_limit():
