@@ -204,6 +204,23 @@ int place_samples(const float *t_n, const float *t_f, const int32_t *n_vox,
                   float *dt, int32_t *ray_id, int64_t s_cap, int64_t *s_total_dev,
                   int64_t *s_total_host, void *ws, size_t ws_bytes, void *stream);
 
+/* place_samples without a workspace argument, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid allocation).  Same arguments, outputs and
+ * errors as place_samples except ws / ws_bytes: the scan's block partials
+ * live in a static device array of the library (2 * 16384 + 1 int64,
+ * 256 KiB per device, held until the process ends), so n_rays is at most
+ * 4 194 304 (TSDFS_EINVAL above that, nothing launched).  The array's
+ * device address is looked up once per device, on the first call there.
+ * No allocation.  Every call on one device shares that array: calls that
+ * overlap on one device (different streams or host threads) race and must
+ * be serialised by the caller. */
+int place_samples_noalloc(const float *t_n, const float *t_f, const int32_t *n_vox,
+                          const uint8_t *status, int64_t n_rays, int32_t rho_num,
+                          int32_t rho_den, int32_t n_min, int32_t n_max, int32_t *counts,
+                          int32_t *offsets, float *t, float *dt, int32_t *ray_id, int64_t s_cap,
+                          int64_t *s_total_dev, int64_t *s_total_host, void *stream);
+
 /* Hierarchical-sampling baseline (the comparison sampler of Sec. 2.2 and the
  * tables; coarse + fine by inverse transform sampling).
  * hs_coarse: n_coarse samples per ray at the midpoints of n_coarse equal

@@ -48,6 +48,8 @@ SIGNATURES = {
     "place_samples_ws_bytes": [c_int64, P],
     "place_samples": [P, P, P, P, c_int64, c_int32, c_int32, c_int32, c_int32, P, P, P, P, P,
                       c_int64, P, P, P, c_size_t, P],
+    "place_samples_noalloc": [P, P, P, P, c_int64, c_int32, c_int32, c_int32, c_int32, P, P, P, P,
+                              P, c_int64, P, P, P],
     "hs_coarse": [P, P, c_int64, c_int32, P, P, P],
     "hs_upsample": [P, P, P, c_int64, c_int32, c_int32, c_float, P, P, P, P, P],
     "tsdf_bound_stats": [P, P, P, P, P, P, c_int64, P, P],

@@ -1,10 +1,15 @@
 // Adaptive sample placement (count -> prefix sum -> placement) and the
 // hierarchical-sampling baseline's coarse/fine placement.
+#include <mutex>
+
 #include "common.hpp"
 
 namespace tsdfs {
 
 constexpr int kPlaceBlock = 256;
+// place_samples_noalloc: rays per call at most (its static block partials)
+constexpr int64_t kNoAllocMaxBlocks = 16384;
+constexpr int64_t kNoAllocMaxRays = kNoAllocMaxBlocks * kPlaceBlock;   // 4 194 304
 
 // Inclusive scan across the 64 lanes of a wave.
 template <typename T>
@@ -383,31 +388,23 @@ int place_samples_ws_bytes(int64_t n_rays, size_t *bytes) {
     return TSDFS_OK;
 }
 
-int place_samples(const float *t_n, const float *t_f, const int32_t *n_vox,
-                  const uint8_t *status, int64_t n_rays, int32_t rho_num, int32_t rho_den,
-                  int32_t n_min, int32_t n_max, int32_t *counts, int32_t *offsets, float *t,
-                  float *dt, int32_t *ray_id, int64_t s_cap, int64_t *s_total_dev,
-                  int64_t *s_total_host, void *ws, size_t ws_bytes, void *stream) {
-    TSDFS_CHECK_ARG(n_rays >= 0, "n_rays must be >= 0");
-    TSDFS_CHECK_ARG(rho_num > 0 && rho_den > 0, "rho must be positive");
-    TSDFS_CHECK_ARG(n_min >= 0 && n_max >= n_min && n_max <= 4096, "need 0 <= n_min <= n_max <= 4096");
-    TSDFS_CHECK_ARG(n_rays * (int64_t)n_max < ((int64_t)1 << 31), "n_rays * n_max must be < 2^31");
-    TSDFS_CHECK_ARG(s_cap >= 0, "s_cap must be >= 0");
-    TSDFS_CHECK_ARG(offsets && s_total_dev, "NULL array argument");
-    TSDFS_CHECK_ARG(n_rays == 0 || counts, "NULL counts");
-    TSDFS_CHECK_ARG(s_cap == 0 || (t && dt && ray_id), "NULL sample array");
-    size_t need;
-    place_samples_ws_bytes(n_rays, &need);
-    TSDFS_CHECK_ARG(ws && ws_bytes >= need, "workspace too small (%zu < %zu)", ws_bytes, need);
-    hipStream_t s = as_stream(stream);
-    int64_t nb = (n_rays + kPlaceBlock - 1) / kPlaceBlock;
-    int64_t *block_sum = (int64_t *)ws;
+}  // extern "C"
+
+namespace tsdfs {
+
+// The three launches of a placement with the block partials in ws
+// ((2 nb + 1) int64, nb = ceil(n_rays / 256)); arguments already checked.
+static int place_run(const float *t_n, const float *t_f, const int32_t *n_vox,
+                     const uint8_t *status, int64_t n_rays, int32_t rho_num, int32_t rho_den,
+                     int32_t n_min, int32_t n_max, int32_t *counts, int32_t *offsets, float *t,
+                     float *dt, int32_t *ray_id, int64_t s_cap, int64_t *s_total_dev,
+                     int64_t *s_total_host, int64_t *ws, hipStream_t s) {
+    const int64_t nb = (n_rays + kPlaceBlock - 1) / kPlaceBlock;
+    int64_t *block_sum = ws;
     int64_t *block_off = block_sum + nb;
-    if (n_rays > 0) {
-        TSDFS_CHECK_ARG(t_n && t_f && n_vox && status, "NULL array argument");
+    if (n_rays > 0)
         hipLaunchKernelGGL(k_count, dim3(nb), dim3(kPlaceBlock), 0, s, n_vox, status, n_rays,
                            rho_num, rho_den, n_min, n_max, counts, block_sum);
-    }
     hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(1024), 0, s, block_sum, nb, block_off,
                        s_total_dev, offsets, n_rays);
     if (n_rays > 0)
@@ -425,6 +422,80 @@ int place_samples(const float *t_n, const float *t_f, const int32_t *n_vox,
         }
     }
     return TSDFS_OK;
+}
+
+#define TSDFS_PLACE_CHECKS()                                                                    \
+    TSDFS_CHECK_ARG(n_rays >= 0, "n_rays must be >= 0");                                        \
+    TSDFS_CHECK_ARG(rho_num > 0 && rho_den > 0, "rho must be positive");                       \
+    TSDFS_CHECK_ARG(n_min >= 0 && n_max >= n_min && n_max <= 4096,                             \
+                    "need 0 <= n_min <= n_max <= 4096");                                        \
+    TSDFS_CHECK_ARG(n_rays * (int64_t)n_max < ((int64_t)1 << 31), "n_rays * n_max must be < 2^31"); \
+    TSDFS_CHECK_ARG(s_cap >= 0, "s_cap must be >= 0");                                          \
+    TSDFS_CHECK_ARG(offsets && s_total_dev, "NULL array argument");                            \
+    TSDFS_CHECK_ARG(n_rays == 0 || counts, "NULL counts");                                      \
+    TSDFS_CHECK_ARG(s_cap == 0 || (t && dt && ray_id), "NULL sample array");                    \
+    TSDFS_CHECK_ARG(n_rays == 0 || (t_n && t_f && n_vox && status), "NULL array argument")
+
+// Block partials of place_samples_noalloc: one static array per device,
+// shared by every call on that device (the partials need no clearing: each
+// call writes every entry it reads).  In host code `scratch` names a
+// host-side stand-in; kernels get its device address, looked up once per
+// device with hipGetSymbolAddress.
+static __device__ __align__(256) int64_t scratch[2 * kNoAllocMaxBlocks + 1];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static int64_t *g_scratch[kMaxDevices];
+
+static int scratch_ptr(int64_t **out) {
+    int dev = -1;
+    TSDFS_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) {
+        set_error("device index %d not supported", dev);
+        return TSDFS_EUNSUPPORTED;
+    }
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch[dev]) {
+        void *p = nullptr;
+        TSDFS_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        g_scratch[dev] = (int64_t *)p;
+    }
+    *out = g_scratch[dev];
+    return TSDFS_OK;
+}
+
+}  // namespace tsdfs
+
+extern "C" {
+
+int place_samples(const float *t_n, const float *t_f, const int32_t *n_vox,
+                  const uint8_t *status, int64_t n_rays, int32_t rho_num, int32_t rho_den,
+                  int32_t n_min, int32_t n_max, int32_t *counts, int32_t *offsets, float *t,
+                  float *dt, int32_t *ray_id, int64_t s_cap, int64_t *s_total_dev,
+                  int64_t *s_total_host, void *ws, size_t ws_bytes, void *stream) {
+    TSDFS_PLACE_CHECKS();
+    size_t need;
+    place_samples_ws_bytes(n_rays, &need);
+    TSDFS_CHECK_ARG(ws && ws_bytes >= need, "workspace too small (%zu < %zu)", ws_bytes, need);
+    return place_run(t_n, t_f, n_vox, status, n_rays, rho_num, rho_den, n_min, n_max, counts,
+                     offsets, t, dt, ray_id, s_cap, s_total_dev, s_total_host, (int64_t *)ws,
+                     as_stream(stream));
+}
+
+int place_samples_noalloc(const float *t_n, const float *t_f, const int32_t *n_vox,
+                          const uint8_t *status, int64_t n_rays, int32_t rho_num,
+                          int32_t rho_den, int32_t n_min, int32_t n_max, int32_t *counts,
+                          int32_t *offsets, float *t, float *dt, int32_t *ray_id, int64_t s_cap,
+                          int64_t *s_total_dev, int64_t *s_total_host, void *stream) {
+    TSDFS_PLACE_CHECKS();
+    TSDFS_CHECK_ARG(n_rays <= kNoAllocMaxRays, "n_rays = %lld exceeds the static workspace's "
+                    "maximum of %lld rays", (long long)n_rays, (long long)kNoAllocMaxRays);
+    int64_t *ws = nullptr;
+    int rc = scratch_ptr(&ws);
+    if (rc != TSDFS_OK) return rc;
+    return place_run(t_n, t_f, n_vox, status, n_rays, rho_num, rho_den, n_min, n_max, counts,
+                     offsets, t, dt, ray_id, s_cap, s_total_dev, s_total_host, ws,
+                     as_stream(stream));
 }
 
 int hs_coarse(const float *t_in, const float *t_out, int64_t n_rays, int32_t n_coarse, float *t,

@@ -159,10 +159,12 @@ def place_ws_bytes(n_rays):
     return b.value
 
 
-def place(bounds, rho_num, rho_den, n_min, n_max, s_cap=None, sync=True, ws=None):
+def place(bounds, rho_num, rho_den, n_min, n_max, s_cap=None, sync=True, ws=None, noalloc=False):
     """Adaptive placement.  With sync=True the total is read back and the
     sample arrays are trimmed to it; otherwise arrays of s_cap are returned
-    together with the device total."""
+    together with the device total.  noalloc=True calls the entry point
+    whose scan partials live in the library's static device array (no
+    workspace)."""
     R = bounds["t_n"].shape[0]
     d = _dev()
     if s_cap is None:
@@ -177,9 +179,12 @@ def place(bounds, rho_num, rho_den, n_min, n_max, s_cap=None, sync=True, ws=None
     args = (_p(bounds["t_n"]), _p(bounds["t_f"]), _p(bounds["n_vox"]), _p(bounds["status"]), R,
             rho_num, rho_den, n_min, n_max, _p(counts), _p(offsets), _p(t), _p(dt), _p(ray_id),
             s_cap, _p(s_total), ctypes.byref(host_total) if sync else None)
-    if ws is None:
-        ws = torch.empty(max(place_ws_bytes(R), 8), dtype=torch.uint8, device=d)
-    L.check(L.load().place_samples(*args, _p(ws), ws.numel(), _stream()))
+    if noalloc:
+        L.check(L.load().place_samples_noalloc(*args, _stream()))
+    else:
+        if ws is None:
+            ws = torch.empty(max(place_ws_bytes(R), 8), dtype=torch.uint8, device=d)
+        L.check(L.load().place_samples(*args, _p(ws), ws.numel(), _stream()))
     out = dict(counts=counts, offsets=offsets, t=t, dt=dt, ray_id=ray_id, s_total=s_total)
     if sync:
         S = host_total.value
