@@ -35,8 +35,8 @@ HBM_PEAK_GBS = 8000.0
 FIELD_SOURCES = {"k_field_fp32": ["field_fp32.hip", "field_common.hpp", "common.hpp", "field.hip"],
                  "k_field_bf16": ["field_bf16.hip", "field_common.hpp", "common.hpp", "field.hip"]}
 TRAFFIC = {
-    "k_field_fp32": {"sha256_16": "6f258e257cf685cb", "fetch_kib": 3.220e+07, "write_kib": 5.791e+07},
-    "k_field_bf16": {"sha256_16": "6e535fc961931faf", "fetch_kib": 1.936e+07, "write_kib": 2.104e+07},
+    "k_field_fp32": {"sha256_16": "f3645b604ee31a4d", "fetch_kib": 3.3976e+07, "write_kib": 5.785e+07},
+    "k_field_bf16": {"sha256_16": "66b265cfcd467783", "fetch_kib": 1.9622e+07, "write_kib": 2.104e+07},
 }
 COPY_SCALE = {"fetch": 2.0, "write": 1.0}
 
@@ -105,9 +105,100 @@ def cpu_baseline(cfg, ro, rv, n_rays, seed=0):
     OR.composite(p["offsets"], v, p["t"], p["dt"], f, g, rgb, cfg.neus_s)
     dt = time.perf_counter() - t0
     return dict(value=n_rays / dt, unit="rays/s", cores=torch.get_num_threads(), kind="oracle",
+                cpu_model=cpu_model(),
                 sample=f"{n_rays} seeded rays of the view through the FP64 oracle render path "
                        f"(bounds, placement, field, compositing) with the oracle's stored flags; "
                        f"{int(p['offsets'][-1])} samples; {dt:.1f} s")
+
+
+def cpu_model():
+    """The host CPU's model name (from /proc/cpuinfo), or None."""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def panorama_leg(steps, warmup):
+    """The large panorama workload in BF16: the 512^3 volume fused from all
+    300 views of 512^2 (78.6 M rays), one equirectangular 2048 x 1024 view
+    (2.1 M rays, 1 to 64 samples per ray, the ragged samples in one
+    persistent field launch), timed like the main step; the field kernel's
+    MFMA fraction from the field stage's events."""
+    import torch
+    from synth.configs import get_config
+    from paper_2311_17878_amd import ops, _lib
+    from paper_2311_17878_amd.pipeline import TsdfRenderer
+    cfg = get_config("c5")
+    g, s = cfg.grid, cfg.sampling
+    t0 = time.time()
+    o, v, d = cfg.integration_rays(progress=lambda k, n: log(f"c5 depth maps {k}/{n}"))
+    ro, rv = cfg.render_rays()
+    log(f"c5 inputs: {o.shape[0]} training rays, {ro.shape[0]} render rays "
+        f"({time.time() - t0:.1f} s)")
+    dev = lambda a: torch.as_tensor(np.ascontiguousarray(a)).cuda()
+    grid = ops.make_grid(g.n, g.lo, g.h, g.d_t, g.d_s, g.nb_radius, g.m_consec)
+    field = ops.Field(cfg.sdf.width, cfg.sdf.n_hidden, cfg.sdf.pe_freqs, cfg.sdf.skip_at,
+                      cfg.sdf.n_feat, cfg.color.n_hidden, cfg.sdf.beta, cfg.in_center,
+                      cfg.in_scale, cfg.sdf_params(), cfg.color_params())
+    R = TsdfRenderer(grid, field, s.rho_num, s.rho_den, s.n_min, s.n_max, cfg.neus_s, s.t_far,
+                     _lib.BF16)
+    o_d, v_d, d_d = dev(o), dev(v), dev(d)
+    del o, v, d
+    nup = torch.zeros(1, dtype=torch.int64, device="cuda")
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    R.integrate(o_d, v_d, d_d, batch=1 << 24, n_updates=nup)
+    e1.record()
+    torch.cuda.synchronize()
+    integ_ms = e0.elapsed_time(e1)
+    n_train = o_d.shape[0]
+    del o_d, v_d, d_d
+    R.finalize(want_v=False)
+    ro_d, rv_d = dev(ro), dev(rv)
+    n_rays = ro.shape[0]
+    for _ in range(warmup):
+        R.render(ro_d, rv_d)
+    torch.cuda.synchronize()
+    ev = {}
+    e0.record()
+    for _ in range(steps):
+        out = R.render(ro_d, rv_d, events=ev)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    stage_ms = {k: float(np.mean([a.elapsed_time(b) for a, b in v_])) for k, v_ in ev.items()}
+    S = int(out["s_total"].item())
+    chk = R.render(ro_d, rv_d, keep=True)
+    counts = chk["place"]["counts"].cpu().numpy()
+    fl_sample, _ = field_flops_per_sample(cfg.sdf, cfg.color)
+    achieved = S * fl_sample / (stage_ms["field"] * 1e-3) / 1e12
+    res = {
+        "workload": f"c5: one {n_rays}-ray equirectangular view; {cfg.notes}; TSDF {g.n[0]}^3, "
+                    f"h={g.h:.6f} m; networks as the room's; BF16 products, FP32 accumulation",
+        "precision": "bf16",
+        "integrate": {"rays": n_train, "ms": integ_ms, "rays_per_s": n_train / (integ_ms * 1e-3),
+                      "voxel_updates": int(nup.item())},
+        "ms_per_step": ms, "rays_per_s": n_rays / (ms * 1e-3),
+        "samples_per_ray": {"mean": S / n_rays, "min": int(counts.min()),
+                            "p50": float(np.percentile(counts, 50)),
+                            "p99": float(np.percentile(counts, 99)), "max": int(counts.max()),
+                            "samples": S},
+        "stage_ms": stage_ms,
+        "roofline": {"kernel": "k_field_bf16", "bound": "mfma", "achieved": achieved,
+                     "peak": PEAK_TFLOPS["bf16"], "unit": "TFLOP/s",
+                     "frac": achieved / PEAK_TFLOPS["bf16"], "flop_per_sample": fl_sample},
+    }
+    log(f"c5 panorama (bf16): {ms:.2f} ms/step, {n_rays / ms * 1e3:.0f} rays/s, "
+        f"{S / n_rays:.2f} samples/ray, field {achieved:.0f} TFLOP/s")
+    del R, field, chk, out, ro_d, rv_d
+    torch.cuda.empty_cache()
+    return res
 
 
 def stage_hbm(stage_ms, n_rays, S, total_steps):
@@ -156,6 +247,8 @@ def main():
                     help="skip the sampling-density sweep")
     ap.add_argument("--no-two-level", dest="two_level", action="store_false",
                     help="skip the two-level volume leg")
+    ap.add_argument("--no-c5", dest="c5", action="store_false",
+                    help="skip the panorama leg (512^3 volume from 300 views, 2.1 M-ray view, BF16)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a device-to-device copy of MIB MiB (to scale HBM counters)")
     args = ap.parse_args()
@@ -731,6 +824,9 @@ def main():
         for v_ in result.get("rho_sweep", {}).values():
             v_["speedup_vs_hs"] = hs_ms / v_["ms_per_step"]
         log(f"hs 64+64: {hs_ms:.2f} ms/step")
+
+    if args.c5 and cfg.name in ("c2", "c3", "c4"):
+        result["c5_panorama_bf16"] = panorama_leg(max(3, args.steps // 2), 1)
 
     if not args.no_cpu_baseline:
         try:
