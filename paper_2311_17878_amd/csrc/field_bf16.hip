@@ -19,16 +19,13 @@
 // transposed weights), the feature vector as BF16, both in accumulator
 // layout; the encoding, its derivative and the reverse-pass values on the
 // encoding rows stay FP32 in the same slot.
-#include "field_common.hpp"
+#include "field_bf16_layout.hpp"
 
 namespace tsdfs {
 
-constexpr int kBT = kBTile;                   // samples per tile
-constexpr int kCB = kBT / 32;                 // 32-sample column blocks per tile
 constexpr int kBWaves = 4;
 constexpr int kBThreads = kBWaves * 64;
 constexpr int kColGroups = kBWaves / 4;       // waves sharing a row pair
-constexpr int kStride = 280;                  // bf16 elements per sample row in LDS
 
 typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
 typedef float floatx2 __attribute__((ext_vector_type(2)));
@@ -101,7 +98,7 @@ __device__ __forceinline__ void gemm_t(const BLayer &L, const __bf16 *act,
     unsigned ao[NT];
     ao[0] = (unsigned)opq(s.t0 * K16 * 64 + lane);
     if (NT == 2) ao[NT - 1] = (unsigned)opq(s.t1 * K16 * 64 + lane);
-    const __bf16 *bp = act + (s.c0 * 32 + col) * kStride + khalf * 8;
+    const __bf16 *bp = act + act_bop(s.c0, 0, col, khalf, 0);
     bf16x8 a0[NT], a1[NT], a2[NT], b0[NC], b1[NC], b2[NC];
     auto loadA = [&](bf16x8 (&a)[NT], int k) __attribute__((always_inline)) {
 #pragma unroll
@@ -109,7 +106,7 @@ __device__ __forceinline__ void gemm_t(const BLayer &L, const __bf16 *act,
     };
     auto loadB = [&](bf16x8 (&b)[NC], int k) __attribute__((always_inline)) {
 #pragma unroll
-        for (int j = 0; j < NC; ++j) b[j] = *(const bf16x8 *)(bp + j * 32 * kStride + k * 16);
+        for (int j = 0; j < NC; ++j) b[j] = *(const bf16x8 *)(bp + act_bop(0, j, 0, 0, k));
     };
     auto load = [&](bf16x8 (&a)[NT], bf16x8 (&b)[NC], int k) __attribute__((always_inline)) {
         loadA(a, k);
@@ -237,15 +234,6 @@ __device__ __forceinline__ void blocks(const Split &s, Ld ld, Use use) {
         blocks_t<1, kCB>(s, ld, use);
 }
 
-// Scratch offsets in uint4: softplus' codes [layer][tile][c][lane] (16
-// bytes), then the features [tile][c][lane] (16 bf16, two uint4).
-__device__ __forceinline__ int ssp(int l, int t, int c, int lane) {
-    return ((l * 8 + t) * kCB + c) * 64 + lane;
-}
-__device__ __forceinline__ int sft(int n_hidden, int t, int c, int lane) {
-    return n_hidden * 8 * kCB * 64 + ((t * kCB + c) * 64 + lane) * 2;
-}
-
 // 8-bit code of softplus' (in [0, 1]): round(255 sigma), from 255 sigma.
 __device__ __forceinline__ uint32_t pk_u8(float a, float b, float c, float d) {
     uint32_t r = __builtin_amdgcn_cvt_pk_u8_f32(a, 0, 0u);
@@ -259,7 +247,7 @@ __device__ __forceinline__ float u8f(uint32_t w, int byte) {
 
 // Store rows r0..r0+3 of sample cc (two packed bf16 pairs).
 __device__ __forceinline__ void st4(__bf16 *act, int cc, int r0, uint32_t p01, uint32_t p23) {
-    *(uint2 *)(act + cc * kStride + r0) = make_uint2(p01, p23);
+    *(uint2 *)(act + act_at(cc, r0)) = make_uint2(p01, p23);
 }
 
 // Softplus_beta and its derivative from z: with a = beta log2(e) z,
@@ -289,7 +277,7 @@ __device__ __forceinline__ void encode_tile(int tid, const float *s_xh, int pe, 
         if (k < 0) {
             gam[a * kBT + c] = x;
             jac[a * kBT + c] = 1.0f;
-            act[c * kStride + a] = (__bf16)x;
+            act[act_at(c, a)] = (__bf16)x;
             continue;
         }
         const float sc = ldexpf(1.0f, k);
@@ -300,12 +288,12 @@ __device__ __forceinline__ void encode_tile(int tid, const float *s_xh, int pe, 
         jac[js * kBT + c] = sc * cs;
         gam[jc * kBT + c] = cs;
         jac[jc * kBT + c] = -sc * sn;
-        act[c * kStride + js] = (__bf16)sn;
-        act[c * kStride + jc] = (__bf16)cs;
+        act[act_at(c, js)] = (__bf16)sn;
+        act[act_at(c, jc)] = (__bf16)cs;
     }
     const int d_gamma = 3 + 6 * pe, n = k_pad - d_gamma;
     for (int idx = tid; idx < n * kBT; idx += kBThreads)
-        act[(idx / n) * kStride + d_gamma + idx % n] = (__bf16)0.0f;
+        act[act_at(idx / n, d_gamma + idx % n)] = (__bf16)0.0f;
 }
 
 // act rows [r0, r0 + d_gamma) <- gam (the re-injected encoding); each thread
@@ -323,7 +311,7 @@ __device__ __forceinline__ void inject_gamma(int tid, __bf16 *act, int r0, int d
 #pragma unroll
     for (int i = 0; i < kGammaRows / kRowsPerPass; ++i) {
         const int j = j0 + kRowsPerPass * i;
-        if (j < d_gamma) act[c * kStride + r0 + j] = (__bf16)x[i];
+        if (j < d_gamma) act[act_at(c, r0 + j)] = (__bf16)x[i];
     }
 }
 
@@ -355,7 +343,7 @@ __device__ __forceinline__ void gamma_grad_reduce(int tid, const float *eg, cons
 __device__ __forceinline__ void zero_rows(int tid, __bf16 *act, int r0, int r1) {
     const int n = r1 - r0;
     for (int idx = tid; idx < n * kBT; idx += kBThreads)
-        act[(idx / n) * kStride + r0 + idx % n] = (__bf16)0.0f;
+        act[act_at(idx / n, r0 + idx % n)] = (__bf16)0.0f;
 }
 
 template <bool FULL>
@@ -380,9 +368,9 @@ k_field_bf16(const BPlan P, const float *__restrict__ o, const float *__restrict
     // [8][kCB][64][32 B], then FP32 eg, gam, jac [64][kBT]
     float *slot = ws + (size_t)blockIdx.x * bf16_slot_floats(P.n_hidden);
     uint4 *scr = (uint4 *)slot;
-    float *eg = slot + (size_t)(P.n_hidden * 8 * kCB * 64 + 8 * kCB * 128) * 4;
-    float *gam = eg + kGammaRows * kBT;
-    float *jac = gam + kGammaRows * kBT;
+    float *eg = slot + eg_offset(P.n_hidden);
+    float *gam = slot + gam_offset(P.n_hidden);
+    float *jac = slot + jac_offset(P.n_hidden);
     const float kb = P.kb, c1 = P.c1;
     const int pe = (P.d_gamma - 3) / 6;
 
@@ -555,7 +543,7 @@ k_field_bf16(const BPlan P, const float *__restrict__ o, const float *__restrict
             int c = idx / 9, j = idx % 9;
             float x = j < 3 ? s_xh[j * kBT + c]
                             : (j < 6 ? s_v[(j - 3) * kBT + c] : s_g[(j - 6) * kBT + c]);
-            act[c * kStride + P.n_feat + j] = (__bf16)x;
+            act[act_at(c, P.n_feat + j)] = (__bf16)x;
         }
         if (P.n_feat + 9 < P.col[0].K16 * 16) zero_rows(tid, act, P.n_feat + 9, P.col[0].K16 * 16);
         __syncthreads();
