@@ -135,10 +135,76 @@ __device__ __forceinline__ bool int_update(const LatGrid &g, IntRay &q, int64_t 
     return true;
 }
 
+// walk_exit_axis and walk_step with every per-axis array read at a
+// compile-time index (selects instead of a runtime index, which would put
+// the lane's walk state in scratch memory); the same decisions and values.
+__device__ __forceinline__ int exit_axis_reg(const Walk &w) {
+    const int64_t n0 = w.num[0], n1 = w.num[1], n2 = w.num[2];
+    const int64_t d0 = w.den[0], d1 = w.den[1], d2 = w.den[2];
+    const bool c1 = n1 * d0 < n0 * d1;
+    const int64_t na = c1 ? n1 : n0, da = c1 ? d1 : d0;
+    const bool c2 = n2 * da < na * d2;
+    return c2 ? 2 : (c1 ? 1 : 0);
+}
+
 __device__ __forceinline__ void int_advance(const LatGrid &g, IntRay &q) {
-    int a = walk_exit_axis(q.w);
-    q.A -= q.dA[a];
-    if (!walk_step(g, q.w, a)) q.alive = false;
+    const int a = exit_axis_reg(q.w);
+    bool inside = true;
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+        if (a == b) {
+            q.A -= q.dA[b];
+            q.w.en_num = q.w.num[b];
+            q.w.en_den = q.w.den[b];
+            q.w.i[b] += q.w.step[b];
+            q.w.num[b] += (int32_t)g.H;
+            inside = q.w.i[b] >= 0 && q.w.i[b] < g.n[b];
+        }
+    }
+    if (!inside) q.alive = false;
+}
+
+// Cross-lane moves of the wave64 scans on DPP (no LDS round trip): lane i
+// receives lane i - n of its 16-lane row (row_shr), lane 15 of the previous
+// row (row_bcast15, rows 1 and 3), lane 31 (row_bcast31, rows 2 and 3), or
+// lane i -/+ 1 of the wave (wave_shr1 / wave_shl1); lanes without a source
+// receive 0.
+enum : int {
+    kDppRowShr1 = 0x111, kDppRowShr2 = 0x112, kDppRowShr4 = 0x114, kDppRowShr8 = 0x118,
+    kDppWaveShl1 = 0x130, kDppWaveShr1 = 0x138, kDppRowBcast15 = 0x142, kDppRowBcast31 = 0x143
+};
+
+template <int CTRL, int ROW_MASK = 0xf>
+__device__ __forceinline__ int32_t dpp32(int32_t x) {
+    return __builtin_amdgcn_update_dpp(0, x, CTRL, ROW_MASK, 0xf, true);
+}
+
+template <int CTRL, int ROW_MASK = 0xf>
+__device__ __forceinline__ int64_t dpp64(int64_t x) {
+    const uint32_t lo = (uint32_t)dpp32<CTRL, ROW_MASK>((int32_t)(uint32_t)x);
+    const int32_t hi = dpp32<CTRL, ROW_MASK>((int32_t)(x >> 32));
+    return (int64_t)(((uint64_t)(uint32_t)hi << 32) | lo);
+}
+
+// inclusive prefix sum / prefix max over the 64 lanes
+__device__ __forceinline__ int64_t wave_scan_add(int64_t x) {
+    x += dpp64<kDppRowShr1>(x);
+    x += dpp64<kDppRowShr2>(x);
+    x += dpp64<kDppRowShr4>(x);
+    x += dpp64<kDppRowShr8>(x);
+    x += dpp64<kDppRowBcast15, 0xa>(x);
+    x += dpp64<kDppRowBcast31, 0xc>(x);
+    return x;
+}
+
+__device__ __forceinline__ int32_t wave_scan_max(int32_t x) {   // x >= 0
+    x = max(x, dpp32<kDppRowShr1>(x));
+    x = max(x, dpp32<kDppRowShr2>(x));
+    x = max(x, dpp32<kDppRowShr4>(x));
+    x = max(x, dpp32<kDppRowShr8>(x));
+    x = max(x, dpp32<kDppRowBcast15, 0xa>(x));
+    x = max(x, dpp32<kDppRowBcast31, 0xc>(x));
+    return x;
 }
 
 // Runs of consecutive lanes with the same key X (the whole wave takes part):
@@ -147,19 +213,10 @@ __device__ __forceinline__ void int_advance(const LatGrid &g, IntRay &q) {
 // the run heads).
 __device__ __forceinline__ bool wave_run(int64_t X, int64_t s32, int lane, int64_t &run_sum,
                                          uint32_t &run_len) {
-    const int64_t Xp = __shfl_up(X, 1);
-    const int64_t Xn = __shfl_down(X, 1);
-    int head = (lane == 0 || Xp != X) ? lane : 0;
-    int64_t P = s32;
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-        const int64_t tp = __shfl_up(P, d);
-        const int th = __shfl_up(head, d);
-        if (lane >= d) {
-            P += tp;
-            head = th > head ? th : head;
-        }
-    }
+    const int64_t Xp = dpp64<kDppWaveShr1>(X);   // lane - 1 (lane 0: unused)
+    const int64_t Xn = dpp64<kDppWaveShl1>(X);   // lane + 1 (lane 63: unused)
+    const int head = wave_scan_max((lane == 0 || Xp != X) ? lane : 0);
+    const int64_t P = wave_scan_add(s32);
     const int64_t before = __shfl(P, head > 0 ? head - 1 : 0);
     run_sum = P - (head > 0 ? before : 0);
     run_len = (uint32_t)(lane - head + 1);
@@ -168,7 +225,7 @@ __device__ __forceinline__ bool wave_run(int64_t X, int64_t s32, int lane, int64
 
 // the last lane of each run of equal keys (no sums)
 __device__ __forceinline__ bool wave_run_tail(int64_t X, int lane) {
-    const int64_t Xn = __shfl_down(X, 1);
+    const int64_t Xn = dpp64<kDppWaveShl1>(X);
     return lane == 63 || Xn != X;
 }
 
