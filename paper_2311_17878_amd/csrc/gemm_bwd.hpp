@@ -40,13 +40,16 @@ template <> struct Prec<true> {
 
 // An operand as a function of (i, k): i indexes output rows (A) or output
 // columns (B), k the reduction.  kcont: element at p[i ld + k], else
-// p[k ld + i].  Elements with i >= n_i or k >= n_k read as zero.
+// p[k ld + i].  Elements with i >= n_i or k >= n_k read as zero.  The
+// elements are FP32 or BF16 in memory (the loader's S); a BF16 operand only
+// feeds BF16 products, which round FP32 inputs to BF16 anyway, so storing
+// it rounded gives the same products.
 struct Opnd {
-    const float *p;
+    const void *p;
     int ld, n_i, n_k;
 };
 
-enum { LD_KVEC = 0, LD_KSCALAR = 1, LD_ICONT = 2 };
+enum { LD_KVEC = 0, LD_ICONT = 2 };
 
 // Global -> registers -> LDS for one NI x BK tile, V consecutive k per item
 // (one 16-byte LDS store), NI * BK / V / 256 items per thread.  Loads are
@@ -54,11 +57,16 @@ enum { LD_KVEC = 0, LD_KSCALAR = 1, LD_ICONT = 2 };
 // operand's first element instead and is zeroed when the registers are
 // written to LDS, so the loads of a step stay in flight together until the
 // store (the entries of an item that are valid form a prefix in k).
-template <bool BF, int NI, int MODE>
+// S = float: FP32 elements in memory; S = __bf16 (BF16 products only):
+// BF16 elements, kept as raw 16-bit words until the store.
+template <bool BF, int NI, int MODE, typename S = float>
 struct Loader {
     typedef Prec<BF> P;
+    static constexpr bool SB = sizeof(S) == 2;
+    static_assert(!SB || BF, "BF16 operands feed BF16 products only");
     static constexpr int ITEMS = NI * (P::BK / P::V) / kThreads;
-    float r[ITEMS][P::V];
+    float r[SB ? 1 : ITEMS][P::V];
+    uint32_t w[SB ? ITEMS : 1][P::V / 2];   // BF16: element pairs (low half first)
     int nv[ITEMS];   // valid entries of each item
 
     __device__ __forceinline__ static void coords(int it, int &row, int &kv) {
@@ -81,40 +89,72 @@ struct Loader {
             n = n < 0 ? 0 : n > P::V ? P::V : n;
             if (i >= o.n_i) n = 0;
             nv[q] = n;
-            if (MODE == LD_KVEC) {
+            if constexpr (SB) {
+                const uint16_t *p = (const uint16_t *)o.p;
+                if (MODE == LD_KVEC) {
+                    // one 16-byte load: ld is a multiple of 8 and >= n_k
+                    // rounded up to 8, so a load that starts below n_k stays
+                    // in its row
+                    const unsigned off = n > 0 ? (unsigned)(i * o.ld + k) : 0u;
+                    const uint4 x = *(const uint4 *)(p + off);
+                    w[q][0] = x.x;
+                    w[q][1] = x.y;
+                    w[q][2] = x.z;
+                    w[q][3] = x.w;
+                } else {
+                    uint32_t e[8];
+#pragma unroll
+                    for (int u = 0; u < 8; ++u)
+                        e[u] = p[u < n ? (unsigned)((k + u) * o.ld + i) : 0u];
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) w[q][u] = e[2 * u] | (e[2 * u + 1] << 16);
+                }
+            } else if (MODE == LD_KVEC) {
                 // 16-byte loads: ld is a multiple of 4 and >= n_k rounded up
                 // to 4, so a load that starts below n_k stays in its row
+                const float *p = (const float *)o.p;
 #pragma unroll
                 for (int u = 0; u < P::V; u += 4) {
                     const unsigned off = u < n ? (unsigned)(i * o.ld + k + u) : 0u;
-                    const float4 x = *(const float4 *)(o.p + off);
+                    const float4 x = *(const float4 *)(p + off);
                     r[q][u] = x.x;
                     r[q][u + 1] = x.y;
                     r[q][u + 2] = x.z;
                     r[q][u + 3] = x.w;
                 }
             } else {
+                const float *p = (const float *)o.p;
 #pragma unroll
-                for (int u = 0; u < P::V; ++u) {
-                    const unsigned off =
-                        u < n ? (unsigned)(MODE == LD_ICONT ? (k + u) * o.ld + i : i * o.ld + k + u)
-                              : 0u;
-                    r[q][u] = o.p[off];
-                }
+                for (int u = 0; u < P::V; ++u)
+                    r[q][u] = p[u < n ? (unsigned)((k + u) * o.ld + i) : 0u];
             }
         }
     }
 
+    // the BF16 pair u of item q with the entries past nv zeroed
+    __device__ __forceinline__ uint32_t pair(int q, int u) const {
+        const uint32_t lo = 2 * u < nv[q] ? 0x0000ffffu : 0u;
+        const uint32_t hi = 2 * u + 1 < nv[q] ? 0xffff0000u : 0u;
+        return w[q][u] & (lo | hi);
+    }
+
     // Sum of this thread's masked entries.  In LD_ICONT mode with NI = 128
     // every item of a thread lies on one row, i = tid % 128, so this is the
-    // thread's share of that row's sum over the step's k (FP32, before any
-    // BF16 rounding).
+    // thread's share of that row's sum over the step's k (FP32 operands:
+    // before any BF16 rounding).
     __device__ __forceinline__ float row_sum() const {
         float s = 0.0f;
 #pragma unroll
         for (int q = 0; q < ITEMS; ++q)
 #pragma unroll
-            for (int u = 0; u < P::V; ++u) s += u < nv[q] ? r[q][u] : 0.0f;
+            for (int u = 0; u < P::V; ++u) {
+                if constexpr (SB) {
+                    const uint32_t x = pair(q, u / 2);
+                    s += __uint_as_float(u % 2 ? x & 0xffff0000u : x << 16);
+                } else {
+                    s += u < nv[q] ? r[q][u] : 0.0f;
+                }
+            }
         return s;
     }
 
@@ -123,16 +163,21 @@ struct Loader {
         for (int q = 0; q < ITEMS; ++q) {
             int row, kv;
             coords(tid + kThreads * q, row, kv);
-            float x[P::V];
-#pragma unroll
-            for (int u = 0; u < P::V; ++u) x[u] = u < nv[q] ? r[q][u] : 0.0f;
-            if constexpr (BF) {
-                bf16x8 h;
-#pragma unroll
-                for (int u = 0; u < 8; ++u) h[u] = (__bf16)x[u];   // RNE
-                *(bf16x8 *)(lds + row * P::LS + kv) = h;
+            if constexpr (SB) {
+                *(uint4 *)(lds + row * P::LS + kv) =
+                    make_uint4(pair(q, 0), pair(q, 1), pair(q, 2), pair(q, 3));
             } else {
-                *(float4 *)(lds + row * P::LS + kv) = make_float4(x[0], x[1], x[2], x[3]);
+                float x[P::V];
+#pragma unroll
+                for (int u = 0; u < P::V; ++u) x[u] = u < nv[q] ? r[q][u] : 0.0f;
+                if constexpr (BF) {
+                    bf16x8 h;
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) h[u] = (__bf16)x[u];   // RNE
+                    *(bf16x8 *)(lds + row * P::LS + kv) = h;
+                } else {
+                    *(float4 *)(lds + row * P::LS + kv) = make_float4(x[0], x[1], x[2], x[3]);
+                }
             }
         }
     }
@@ -195,7 +240,8 @@ __device__ __forceinline__ void mma_tile(const typename Prec<BF>::T *As,
 // sum over k in [k_begin, k_end) of A(i0 + ., k) B(j0 + ., k) into acc.
 // With a_sum (A in LD_ICONT mode), *a_sum also receives this thread's share
 // of sum_k A(i0 + tid % 128, k) (FP32; tid and tid + 128 share a row).
-template <bool BF, int RB, int CB, int WC, int AMODE, int BMODE>
+template <bool BF, int RB, int CB, int WC, int AMODE, int BMODE, typename SA = float,
+          typename SB = float>
 __device__ __forceinline__ void tile_product(const Opnd &A, const Opnd &B, int i0, int j0,
                                              int k_begin, int k_end, Acc<RB, CB> &acc,
                                              typename Prec<BF>::T *As, typename Prec<BF>::T *Bs,
@@ -207,8 +253,8 @@ __device__ __forceinline__ void tile_product(const Opnd &A, const Opnd &B, int i
     for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
         for (int cb = 0; cb < CB; ++cb) acc.a[rb][cb] = (floatx16)(0.0f);
-    Loader<BF, kBM, AMODE> la;
-    Loader<BF, BN, BMODE> lb;
+    Loader<BF, kBM, AMODE, SA> la;
+    Loader<BF, BN, BMODE, SB> lb;
     if (k_begin < k_end) {
         la.load(A, i0, k_begin, tid);
         lb.load(B, j0, k_begin, tid);

@@ -15,6 +15,8 @@
 // fixed-order two-pass reductions, so a call is deterministic.
 #include <math.h>
 
+#include <type_traits>
+
 #include "gemm_bwd.hpp"
 
 namespace tsdfs {
@@ -100,46 +102,65 @@ struct Epi {
     float ln2_beta = 0.0f;   // ln 2 / beta (E_SOFTPLUS)
     int split = 0, S = 0;
     const float *drgb = nullptr;
+    // bit w set: output o_w is stored in BF16 (rounded to nearest even);
+    // bf_i0: i0 is BF16 (E_MASK only)
+    unsigned bf_out = 0;
+    bool bf_i0 = false;
 };
 
-template <int MODE>
+// BF: the epilogue of a BF16 product (the only kind that may write BF16)
+template <int W, bool BF>
+__device__ __forceinline__ void put(const Epi &e, float *o, unsigned idx, float v) {
+    if (BF && (e.bf_out & (1u << W)))
+        ((__bf16 *)o)[idx] = (__bf16)v;
+    else
+        o[idx] = v;
+}
+
+template <int MODE, bool BF>
 __device__ __forceinline__ void apply(const Epi &e, int r, int n, float v) {
     // every row-major buffer indexes with 32 bits (rows * ld < 2^31)
     const unsigned a0 = (unsigned)(r * e.ld0 + n);
     if constexpr (MODE == E_STORE) {
-        e.o0[a0] = v;
+        put<0, BF>(e, e.o0, a0, v);
     } else if constexpr (MODE == E_BIAS) {
-        e.o0[a0] = v + e.bias[n];
+        put<0, BF>(e, e.o0, a0, v + e.bias[n]);
     } else if constexpr (MODE == E_SOFTPLUS) {
         const float z = v + e.bias[n];
-        e.o0[a0] = z;
-        e.o1[(unsigned)(r * e.ld1 + n)] = e.s0 * softplus_hw(z, e.beta, e.ln2_beta);
-        if (e.o2) e.o2[(unsigned)(r * e.ld2 + n)] = e.i0[n] * sig_hw(e.beta * z);
+        put<0, BF>(e, e.o0, a0, z);
+        put<1, BF>(e, e.o1, (unsigned)(r * e.ld1 + n), e.s0 * softplus_hw(z, e.beta, e.ln2_beta));
+        if (e.o2) put<2, BF>(e, e.o2, (unsigned)(r * e.ld2 + n), e.i0[n] * sig_hw(e.beta * z));
     } else if constexpr (MODE == E_REV) {
         const float x = e.s0 * v;
         if (n < e.split) {
-            e.o0[a0] = x;
-            e.o1[(unsigned)(r * e.ld1 + n)] = x * sig_hw(e.beta * e.i0[(unsigned)(r * e.ldi0 + n)]);
+            put<0, BF>(e, e.o0, a0, x);
+            put<1, BF>(e, e.o1, (unsigned)(r * e.ld1 + n),
+                   x * sig_hw(e.beta * e.i0[(unsigned)(r * e.ldi0 + n)]));
         } else {
-            e.o2[(unsigned)(r * e.ld2 + (n - e.split))] = x;
+            put<2, BF>(e, e.o2, (unsigned)(r * e.ld2 + (n - e.split)), x);
         }
     } else if constexpr (MODE == E_RELU) {
-        e.o0[a0] = fmaxf(v + e.bias[n], 0.0f);
+        put<0, BF>(e, e.o0, a0, fmaxf(v + e.bias[n], 0.0f));
     } else if constexpr (MODE == E_RGB) {
         const float c = sig_hw(v + e.bias[n]);
-        e.o0[a0] = c;
-        e.o1[(unsigned)(r * e.ld1 + n)] = r < e.S ? e.drgb[(unsigned)(3 * r + n)] * c * (1.0f - c) : 0.0f;
+        put<0, BF>(e, e.o0, a0, c);
+        put<1, BF>(e, e.o1, (unsigned)(r * e.ld1 + n),
+               r < e.S ? e.drgb[(unsigned)(3 * r + n)] * c * (1.0f - c) : 0.0f);
     } else if constexpr (MODE == E_MASK) {
-        e.o0[a0] = e.i0[(unsigned)(r * e.ldi0 + n)] > 0.0f ? v : 0.0f;
+        const unsigned ai = (unsigned)(r * e.ldi0 + n);
+        const float m = (BF && e.bf_i0) ? __uint_as_float((uint32_t)((const uint16_t *)e.i0)[ai] << 16)
+                                : e.i0[ai];
+        put<0, BF>(e, e.o0, a0, m > 0.0f ? v : 0.0f);
     } else if constexpr (MODE == E_SO) {
         const float sp = sig_hw(e.beta * e.i0[(unsigned)(r * e.ldi0 + n)]);
         const float ee = e.i1 ? e.i1[(unsigned)(r * e.ldi1 + n)] : e.bias[n];
-        e.o0[a0] = v * sp;
-        e.o1[(unsigned)(r * e.ld1 + n)] = v * ee * (e.beta * sp * (1.0f - sp));
+        put<0, BF>(e, e.o0, a0, v * sp);
+        put<1, BF>(e, e.o1, (unsigned)(r * e.ld1 + n), v * ee * (e.beta * sp * (1.0f - sp)));
     } else {   // E_FO
         if (n < e.split)
-            e.o0[a0] = e.s0 * v * sig_hw(e.beta * e.i0[(unsigned)(r * e.ldi0 + n)]) +
-                       e.i1[(unsigned)(r * e.ldi1 + n)];
+            put<0, BF>(e, e.o0, a0,
+                   e.s0 * v * sig_hw(e.beta * e.i0[(unsigned)(r * e.ldi0 + n)]) +
+                       e.i1[(unsigned)(r * e.ldi1 + n)]);
     }
 }
 
@@ -187,7 +208,7 @@ __device__ __forceinline__ void epilogue_grad(const Epi &e, const bwd::Acc<RB, C
 }
 
 // the epilogue of a whole tile, its mode chosen once per workgroup
-template <int RB, int CB, int WC>
+template <bool BF, int RB, int CB, int WC>
 __device__ __forceinline__ void epilogue(const Epi &e, const bwd::Acc<RB, CB> &acc, int i0, int j0,
                                          int M, int N) {
     if (e.mode == E_GRAD) {   // launched with one column tile of one wave's width
@@ -197,7 +218,7 @@ __device__ __forceinline__ void epilogue(const Epi &e, const bwd::Acc<RB, CB> &a
 #define TSDFS_EPI_CASE(m)                                                                   \
     case m:                                                                                 \
         bwd::for_each<RB, CB, WC>(acc, i0, j0, M, N,                                        \
-                                  [&](int r, int n, float v) { apply<m>(e, r, n, v); });    \
+                                  [&](int r, int n, float v) { apply<m, BF>(e, r, n, v); });\
         break;
     switch (e.mode) {
         TSDFS_EPI_CASE(E_STORE)
@@ -221,7 +242,9 @@ __device__ __forceinline__ void epilogue(const Epi &e, const bwd::Acc<RB, CB> &a
 // by multiples of 8, so they share an XCD and its L2.
 constexpr int kXcd = 8;
 
-template <bool BF, int RB, int CB, int WC>
+// SA: the A operand's element type in memory; the B operand (staged
+// weights) is BF16 for BF16 products, else FP32
+template <bool BF, int RB, int CB, int WC, typename SA>
 __global__ void __launch_bounds__(bwd::kThreads) k_row(Opnd A, Opnd B, int R, int N, int j_base,
                                                        int n_rt, int n_nt, Epi e) {
     typedef bwd::Prec<BF> P;
@@ -233,15 +256,16 @@ __global__ void __launch_bounds__(bwd::kThreads) k_row(Opnd A, Opnd B, int R, in
     if (rt >= n_rt) return;   // uniform over the workgroup
     const int i0 = rt * bwd::kBM, j0 = j_base + nt * BN;
     bwd::Acc<RB, CB> acc;
-    bwd::tile_product<BF, RB, CB, WC, bwd::LD_KVEC, bwd::LD_KVEC>(A, B, i0, j0, 0, A.n_k, acc, As,
-                                                                  Bs);
-    epilogue<RB, CB, WC>(e, acc, i0, j0, R, N);
+    typedef typename std::conditional<BF, __bf16, float>::type SW;
+    bwd::tile_product<BF, RB, CB, WC, bwd::LD_KVEC, bwd::LD_KVEC, SA, SW>(A, B, i0, j0, 0, A.n_k,
+                                                                          acc, As, Bs);
+    epilogue<BF, RB, CB, WC>(e, acc, i0, j0, R, N);
 }
 
 // Weight gradients: partial products per chunk of rows; the workgroups of
 // the first column tile also form the chunk's column sums of A (the bias
 // gradients) when bpart is set.
-template <bool BF>
+template <bool BF, typename SA, typename SB>
 __global__ void __launch_bounds__(bwd::kThreads, 2) k_wgrad(Opnd A, Opnd B, int M, int N, int R,
                                                          int kc, int n_mt, int n_nt, int n_ch,
                                                          float *__restrict__ part,
@@ -259,9 +283,8 @@ __global__ void __launch_bounds__(bwd::kThreads, 2) k_wgrad(Opnd A, Opnd B, int 
     const bool sums = bpart != nullptr && nt == 0;
     float a_sum = 0.0f;
     bwd::Acc<2, 2> acc;
-    bwd::tile_product<BF, 2, 2, 2, bwd::LD_ICONT, bwd::LD_ICONT>(A, B, i0, j0, k_begin, k_end,
-                                                                 acc, As, Bs,
-                                                                 sums ? &a_sum : nullptr);
+    bwd::tile_product<BF, 2, 2, 2, bwd::LD_ICONT, bwd::LD_ICONT, SA, SB>(
+        A, B, i0, j0, k_begin, k_end, acc, As, Bs, sums ? &a_sum : nullptr);
     float *out = part + (size_t)ch * M * N;
     bwd::for_each<2, 2, 2>(acc, i0, j0, M, N,
                            [&](int m, int n, float v) { out[(unsigned)(m * N + n)] = v; });
@@ -310,60 +333,76 @@ struct Ctx {
     float *bpart;       // bias-gradient partials [kMaxChunks][<= wide]
 };
 
-static bool vec_ok(const float *p, int ld, int k) {
-    return ((uintptr_t)p % 16 == 0) && ld % 4 == 0 && ld >= round4(k);
+// 16-byte loads of 4 FP32 or 8 BF16 elements stay inside a row
+static bool vec_ok(const void *p, int ld, int k, bool bf) {
+    const int v = bf ? 8 : 4;
+    return ((uintptr_t)p % 16 == 0) && ld % v == 0 && ld >= (k + v - 1) / v * v;
 }
 
 // Columns [j_base, j_base + ncols) of a row product in tiles of 32 NB.
-template <bool BF>
+template <bool BF, typename SA>
 static void launch_row(const Ctx &c, int nb, const Opnd &A, const Opnd &B, int R, int N,
                        int j_base, int ncols, const Epi &e) {
     const int n_rt = (R + bwd::kBM - 1) / bwd::kBM;
     const int n_nt = (ncols + 32 * nb - 1) / (32 * nb);
     const unsigned grid = (unsigned)((n_rt + kXcd - 1) / kXcd * kXcd * n_nt);
     if (nb == 4)
-        hipLaunchKernelGGL((k_row<BF, 2, 2, 2>), dim3(grid), dim3(bwd::kThreads), 0, c.st, A, B, R,
+        hipLaunchKernelGGL((k_row<BF, 2, 2, 2, SA>), dim3(grid), dim3(bwd::kThreads), 0, c.st, A, B, R,
                            N, j_base, n_rt, n_nt, e);
     else if (nb == 2)
-        hipLaunchKernelGGL((k_row<BF, 1, 2, 1>), dim3(grid), dim3(bwd::kThreads), 0, c.st, A, B, R,
+        hipLaunchKernelGGL((k_row<BF, 1, 2, 1, SA>), dim3(grid), dim3(bwd::kThreads), 0, c.st, A, B, R,
                            N, j_base, n_rt, n_nt, e);
     else
-        hipLaunchKernelGGL((k_row<BF, 1, 1, 1>), dim3(grid), dim3(bwd::kThreads), 0, c.st, A, B, R,
+        hipLaunchKernelGGL((k_row<BF, 1, 1, 1, SA>), dim3(grid), dim3(bwd::kThreads), 0, c.st, A, B, R,
                            N, j_base, n_rt, n_nt, e);
 }
 
-template <bool BF>
+template <bool BF, typename SA>
 static void row_tiles(const Ctx &c, const Opnd &A, const Opnd &B, int R, int N, const Epi &e) {
     const int nfull = N / 128 * 128, rem = N - nfull;
-    if (nfull > 0) launch_row<BF>(c, 4, A, B, R, N, 0, nfull, e);
-    if (rem > 0) launch_row<BF>(c, rem <= 32 ? 1 : rem <= 64 ? 2 : 4, A, B, R, N, nfull, rem, e);
+    if (nfull > 0) launch_row<BF, SA>(c, 4, A, B, R, N, 0, nfull, e);
+    if (rem > 0)
+        launch_row<BF, SA>(c, rem <= 32 ? 1 : rem <= 64 ? 2 : 4, A, B, R, N, nfull, rem, e);
 }
 
 // C[r][n] (r < R, n < N) = sum_{k < K} A[r lda + k] W[n ldw + k] through the
 // epilogue e.  Both operands must allow 16-byte loads (vec_ok): activations
-// have padded rows, weights are the staged copies.
-static int gemm_row(const Ctx &c, int R, int N, int K, const float *A, int lda, const float *W,
-                    int ldw, const Epi &e) {
+// have padded rows, weights are the staged copies (BF16 for BF16 products).
+// a_bf: A is stored in BF16 (BF16 products only).
+static int gemm_row(const Ctx &c, int R, int N, int K, const void *A, bool a_bf, int lda,
+                    const void *W, int ldw, const Epi &e) {
     if (R <= 0 || N <= 0) return TSDFS_OK;
-    if (!vec_ok(A, lda, K) || !vec_ok(W, ldw, K)) {
+    if (!c.bf16 && (a_bf || e.bf_out || e.bf_i0)) {
+        set_error("internal: BF16 operand or output in an FP32 product");
+        return TSDFS_EHIP;
+    }
+    if (!vec_ok(A, lda, K, a_bf) || !vec_ok(W, ldw, K, c.bf16)) {
         set_error("internal: row product operands not aligned (ld %d / %d, K %d)", lda, ldw, K);
         return TSDFS_EHIP;
     }
     const Opnd a{A, lda, R, K};
     const Opnd b{W, ldw, N, K};
-    if (c.bf16)
-        row_tiles<true>(c, a, b, R, N, e);
+    if (!c.bf16)
+        row_tiles<false, float>(c, a, b, R, N, e);
+    else if (a_bf)
+        row_tiles<true, __bf16>(c, a, b, R, N, e);
     else
-        row_tiles<false>(c, a, b, R, N, e);
+        row_tiles<true, float>(c, a, b, R, N, e);
     TSDFS_LAUNCH_CHECK();
     return TSDFS_OK;
 }
 
 // C[m ldc + n] += sum_{r < R} A[r lda + m] B[r ldb + n]  (m < M, n < N), and
-// with bias: bias[m] += sum_{r < R} A[r lda + m]
-static int gemm_wgrad(const Ctx &c, int R, int M, int N, const float *A, int lda, const float *B,
-                      int ldb, float *C, int ldc, float *bias = nullptr) {
+// with bias: bias[m] += sum_{r < R} A[r lda + m].  a_bf / b_bf: the operand
+// is stored in BF16 (BF16 products only).
+static int gemm_wgrad(const Ctx &c, int R, int M, int N, const void *A, bool a_bf, int lda,
+                      const void *B, bool b_bf, int ldb, float *C, int ldc,
+                      float *bias = nullptr) {
     if (R <= 0 || M <= 0 || N <= 0) return TSDFS_OK;
+    if ((a_bf || b_bf) && !c.bf16) {
+        set_error("internal: BF16 operand in an FP32 product");
+        return TSDFS_EHIP;
+    }
     const int kc = chunk_rows(R), n_ch = (R + kc - 1) / kc;
     const int n_mt = (M + bwd::kBM - 1) / bwd::kBM, n_nt = (N + bwd::kBM - 1) / bwd::kBM;
     if ((size_t)n_ch * M * N > c.part_cap) {
@@ -374,12 +413,20 @@ static int gemm_wgrad(const Ctx &c, int R, int M, int N, const float *A, int lda
     const Opnd b{B, ldb, N, R};
     const unsigned grid = (unsigned)((n_ch + kXcd - 1) / kXcd * kXcd * n_mt * n_nt);
     float *bp = bias ? c.bpart : nullptr;
-    if (c.bf16)
-        hipLaunchKernelGGL(k_wgrad<true>, dim3(grid), dim3(bwd::kThreads), 0, c.st, a, b, M, N, R,
-                           kc, n_mt, n_nt, n_ch, c.part, bp);
+#define TSDFS_WGRAD(BF, SA, SB)                                                            \
+    hipLaunchKernelGGL((k_wgrad<BF, SA, SB>), dim3(grid), dim3(bwd::kThreads), 0, c.st, a, b, M, \
+                       N, R, kc, n_mt, n_nt, n_ch, c.part, bp)
+    if (!c.bf16)
+        TSDFS_WGRAD(false, float, float);
+    else if (a_bf && b_bf)
+        TSDFS_WGRAD(true, __bf16, __bf16);
+    else if (a_bf)
+        TSDFS_WGRAD(true, __bf16, float);
+    else if (b_bf)
+        TSDFS_WGRAD(true, float, __bf16);
     else
-        hipLaunchKernelGGL(k_wgrad<false>, dim3(grid), dim3(bwd::kThreads), 0, c.st, a, b, M, N, R,
-                           kc, n_mt, n_nt, n_ch, c.part, bp);
+        TSDFS_WGRAD(true, float, float);
+#undef TSDFS_WGRAD
     const int mn = M * N;
     hipLaunchKernelGGL(k_chunk_reduce, dim3((unsigned)((mn + 255) / 256)), dim3(256), 0, c.st,
                        c.part, n_ch, mn, N, C, ldc);
@@ -567,22 +614,36 @@ static int network_backward(const tsdfs_field *F, const float *o, const float *v
     auto gW = [&](int l) { return gs + F->w_off[l]; };
     auto gb = [&](int l) { return gs + F->b_off[l]; };
     const float *wf = Wl(nh);   // row 0 of the output layer: the f row
-    // staged weights: Wn = W with rows padded to 4 floats, Wt = W^T likewise
+    // BF16 products: the arrays that only ever enter products as operands
+    // (the SDF layers' inputs X_l, l >= 1, the deltas, the colour network's
+    // activations and the staged weights) are stored in BF16, rounded once
+    // where they are made instead of at every product that reads them: the
+    // same products with half the bytes.
+    const bool sb = bf16;
+    auto wld = [&](int n) { return sb ? (n + 7) / 8 * 8 : round4(n); };
+    // staged weights: Wn = W with padded rows, Wt = W^T likewise (FP32 rows
+    // of a multiple of 4, BF16 rows of a multiple of 8 elements)
     auto stage = [&](const float *Wsrc, int out, int in, float *Wn_, float *Wt_) {
-        const int ldn = round4(in), ldt = round4(out);
+        const int ldn = wld(in), ldt = wld(out);
         map2(out, in, st, [=] __device__(int o_, int i_) {
             const float w = Wsrc[(unsigned)(o_ * in + i_)];
-            Wn_[(unsigned)(o_ * ldn + i_)] = w;
-            Wt_[(unsigned)(i_ * ldt + o_)] = w;
+            const unsigned an = (unsigned)(o_ * ldn + i_), at = (unsigned)(i_ * ldt + o_);
+            if (sb) {
+                ((__bf16 *)Wn_)[an] = (__bf16)w;
+                ((__bf16 *)Wt_)[at] = (__bf16)w;
+            } else {
+                Wn_[an] = w;
+                Wt_[at] = w;
+            }
         });
     };
     for (int l = 0; l <= nh; ++l) stage(Wl(l), F->dout[l], F->din[l], B.Wn[l], B.Wt[l]);
     for (int l = 0; l <= d.col_hidden; ++l)
         stage(Wc + F->cw_off[l], F->cdout[l], F->cdin[l], B.Cn[l], B.Ct[l]);
-    auto ldn = [&](int l) { return round4(F->din[l]); };    // Wn[l]
-    auto ldt = [&](int l) { return round4(F->dout[l]); };   // Wt[l]
-    auto cldn = [&](int l) { return round4(F->cdin[l]); };  // Cn[l]
-    auto cldt = [&](int l) { return round4(F->cdout[l]); }; // Ct[l]
+    auto ldn = [&](int l) { return wld(F->din[l]); };    // Wn[l]
+    auto ldt = [&](int l) { return wld(F->dout[l]); };   // Wt[l]
+    auto cldn = [&](int l) { return wld(F->cdin[l]); };  // Cn[l]
+    auto cldt = [&](int l) { return wld(F->cdout[l]); }; // Ct[l]
 
     // ---- inputs: x_hat and direction per row, then the encoding and its
     // Jacobian per (row, encoding entry)
@@ -641,17 +702,24 @@ static int network_backward(const tsdfs_field *F, const float *o, const float *v
         e.beta = beta;
         e.ln2_beta = kLn2 / beta;
         e.s0 = to_skip ? rs2 : 1.0f;
+        e.bf_out = sb ? 2u : 0u;   // X_{l+1}
         if (l == nh - 1) {
             e.o2 = B.D[nh - 1];
             e.ld2 = W;
             e.i0 = wf;
+            e.bf_out |= sb ? 4u : 0u;
         }
-        BWD(gemm_row(C, R, out, in, B.X[l], l == 0 ? ldg : W, B.Wn[l], ldn(l), e));
+        BWD(gemm_row(C, R, out, in, B.X[l], sb && l > 0, l == 0 ? ldg : W, B.Wn[l], ldn(l), e));
         if (to_skip) {
             float *Xn = B.X[l + 1];
             const float *gam = B.gam;
             map2(R, dg, st, [=] __device__(int r, int j) {
-                Xn[(size_t)r * W + out + j] = rs2 * gam[(size_t)r * ldg + j];
+                const unsigned a = (unsigned)(r * W + out + j);
+                const float x = rs2 * gam[(unsigned)(r * ldg + j)];
+                if (sb)
+                    ((__bf16 *)Xn)[a] = (__bf16)x;
+                else
+                    Xn[a] = x;
             });
         }
     }
@@ -662,7 +730,7 @@ static int network_backward(const tsdfs_field *F, const float *o, const float *v
         e.o0 = B.Y;
         e.ld0 = ldy;
         e.bias = bl(nh);
-        BWD(gemm_row(C, R, ny, W, B.X[nh], W, B.Wn[nh], ldn(nh), e));
+        BWD(gemm_row(C, R, ny, W, B.X[nh], sb, W, B.Wn[nh], ldn(nh), e));
     }
     // ---- reverse pass: E_{l-1} = delta_l W_l (x 1/sqrt2 out of the skip
     // layer), delta_{l-1} = E_{l-1} softplus'(Z_{l-1}); encoding rows apart
@@ -681,7 +749,8 @@ static int network_backward(const tsdfs_field *F, const float *o, const float *v
         e.o2 = B.Eg4;
         e.ld2 = ldg;
         e.beta = beta;
-        BWD(gemm_row(C, R, in, out, B.D[l], W, B.Wt[l], ldt(l), e));
+        e.bf_out = sb ? 2u : 0u;   // delta_{l-1}
+        BWD(gemm_row(C, R, in, out, B.D[l], sb, W, B.Wt[l], ldt(l), e));
     }
     // encoding rows from layer 0, delta_0 W_0 [R, dg], and with the skip
     // layer's share and the encoding's Jacobian, grad f (in the epilogue)
@@ -697,7 +766,7 @@ static int network_backward(const tsdfs_field *F, const float *o, const float *v
         e.ldi0 = ldg;
         e.i1 = B.J;
         e.ldi1 = ldg;
-        BWD(gemm_row(C, R, dg, F->dout[0], B.D[0], W, B.Wt[0], ldt(0), e));
+        BWD(gemm_row(C, R, dg, F->dout[0], B.D[0], sb, W, B.Wt[0], ldt(0), e));
     }
     // ---- colour forward
     {
@@ -720,8 +789,9 @@ static int network_backward(const tsdfs_field *F, const float *o, const float *v
         e.o0 = B.Hc[l];
         e.ld0 = W;
         e.bias = Wc + F->cb_off[l];
-        BWD(gemm_row(C, R, W, in, l == 0 ? B.Cin : B.Hc[l - 1], l == 0 ? ldc : W, B.Cn[l],
-                     cldn(l), e));
+        e.bf_out = sb ? 1u : 0u;
+        BWD(gemm_row(C, R, W, in, l == 0 ? B.Cin : B.Hc[l - 1], sb && l > 0, l == 0 ? ldc : W,
+                     B.Cn[l], cldn(l), e));
     }
     // rgb = sigmoid(H W^T + b); dz_out = d rgb * rgb (1 - rgb) on sample rows
     {
@@ -734,10 +804,10 @@ static int network_backward(const tsdfs_field *F, const float *o, const float *v
         e.bias = Wc + F->cb_off[nc];
         e.S = (int)S;
         e.drgb = d_rgb;
-        BWD(gemm_row(C, R, 3, W, B.Hc[nc - 1], W, B.Cn[nc], cldn(nc), e));
+        BWD(gemm_row(C, R, 3, W, B.Hc[nc - 1], sb, W, B.Cn[nc], cldn(nc), e));
     }
     // ---- colour backward: dW_out += dz^T H ; db += sum dz ; dZ = (dz W_out) [H > 0]
-    BWD(gemm_wgrad(C, R, 3, W, B.dz, 4, B.Hc[nc - 1], W, gc + F->cw_off[nc], W,
+    BWD(gemm_wgrad(C, R, 3, W, B.dz, false, 4, B.Hc[nc - 1], sb, W, gc + F->cw_off[nc], W,
                    gc + F->cb_off[nc]));
     {
         Epi e;
@@ -746,14 +816,16 @@ static int network_backward(const tsdfs_field *F, const float *o, const float *v
         e.ld0 = W;
         e.i0 = B.Hc[nc - 1];
         e.ldi0 = W;
-        BWD(gemm_row(C, R, W, 3, B.dz, 4, B.Ct[nc], cldt(nc), e));
+        e.bf_i0 = sb;
+        BWD(gemm_row(C, R, W, 3, B.dz, false, 4, B.Ct[nc], cldt(nc), e));
     }
     float *dZ = B.T1, *dZn = B.T2;
     for (int l = nc - 1; l >= 0; --l) {
         const int in = F->cdin[l];
         const float *X = l == 0 ? B.Cin : B.Hc[l - 1];
         const int ldx = l == 0 ? ldc : W;
-        BWD(gemm_wgrad(C, R, W, in, dZ, W, X, ldx, gc + F->cw_off[l], in, gc + F->cb_off[l]));
+        BWD(gemm_wgrad(C, R, W, in, dZ, false, W, X, sb && l > 0, ldx, gc + F->cw_off[l], in,
+                       gc + F->cb_off[l]));
         Epi e;
         if (l > 0) {
             e.mode = E_MASK;
@@ -761,11 +833,12 @@ static int network_backward(const tsdfs_field *F, const float *o, const float *v
             e.ld0 = W;
             e.i0 = B.Hc[l - 1];
             e.ldi0 = W;
+            e.bf_i0 = sb;
         } else {
             e.o0 = dZn;   // d Cin [R, cin] (ld ldc)
             e.ld0 = ldc;
         }
-        BWD(gemm_row(C, R, in, W, dZ, W, B.Ct[l], cldt(l), e));
+        BWD(gemm_row(C, R, in, W, dZ, false, W, B.Ct[l], cldt(l), e));
         float *tmp = dZ;
         dZ = dZn;
         dZn = tmp;
@@ -811,12 +884,16 @@ static int network_backward(const tsdfs_field *F, const float *o, const float *v
     // ---- second-order pass (adjoint of the reverse pass), forward in l:
     // delta_bar_0 = gbar_g W_0^T, then per layer E_bar_l = delta_bar sp,
     // Z2_l = delta_bar E_l sp' (E = w_f on the last layer), delta_bar_{l+1} =
-    // E_bar'_l W_{l+1}^T and dW_{l+1} += delta_{l+1}^T E_bar'_l
+    // E_bar'_l W_{l+1}^T and dW_{l+1} += delta_{l+1}^T E_bar'_l.  E_bar only
+    // enters products (BF16 when they are), except the last layer's, whose
+    // column sums give w_f's gradient, and the one below the skip layer,
+    // which is scaled by 1/sqrt2 first (both FP32).
     auto so_epi = [&](int l, float *Eb) {
         Epi e;
         e.mode = E_SO;
         e.o0 = Eb;
         e.ld0 = W;
+        e.bf_out = (sb && l < nh - 1 && l + 1 != skip) ? 1u : 0u;
         e.o1 = B.Z2[l];
         e.ld1 = W;
         e.i0 = B.Z[l];
@@ -831,8 +908,8 @@ static int network_backward(const tsdfs_field *F, const float *o, const float *v
         return e;
     };
     float *Eb = B.T0, *Ebn = B.T1;
-    BWD(gemm_row(C, R, F->dout[0], dg, B.gbar_g, ldg, B.Wn[0], ldn(0), so_epi(0, Eb)));
-    BWD(gemm_wgrad(C, R, F->dout[0], dg, B.D[0], W, B.gbar_g, ldg, gW(0), dg));
+    BWD(gemm_row(C, R, F->dout[0], dg, B.gbar_g, false, ldg, B.Wn[0], ldn(0), so_epi(0, Eb)));
+    BWD(gemm_wgrad(C, R, F->dout[0], dg, B.D[0], sb, W, B.gbar_g, false, ldg, gW(0), dg));
     for (int l = 0; l < nh; ++l) {
         const int out = F->dout[l];
         if (l == nh - 1) {
@@ -848,13 +925,17 @@ static int network_backward(const tsdfs_field *F, const float *o, const float *v
             float *Ep = B.T2;
             const float *Ebl = Eb, *gbg = B.gbar_g;
             map2(R, inn, st, [=] __device__(int r, int j) {
-                Ep[(size_t)r * W + j] =
-                    rs2 * (j < out ? Ebl[(size_t)r * W + j] : gbg[(size_t)r * ldg + (j - out)]);
+                const unsigned a = (unsigned)(r * W + j);
+                const float x = j < out ? Ebl[a] : gbg[(unsigned)(r * ldg + (j - out))];
+                if (sb)
+                    ((__bf16 *)Ep)[a] = (__bf16)(rs2 * x);
+                else
+                    Ep[a] = rs2 * x;
             });
             A = Ep;
         }
-        BWD(gemm_row(C, R, outn, inn, A, W, B.Wn[ln], ldn(ln), so_epi(ln, Ebn)));
-        BWD(gemm_wgrad(C, R, outn, inn, B.D[ln], W, A, W, gW(ln), inn));
+        BWD(gemm_row(C, R, outn, inn, A, sb, W, B.Wn[ln], ldn(ln), so_epi(ln, Ebn)));
+        BWD(gemm_wgrad(C, R, outn, inn, B.D[ln], sb, W, A, sb, W, gW(ln), inn));
         float *tmp = Eb;
         Eb = Ebn;
         Ebn = tmp;
@@ -862,7 +943,7 @@ static int network_backward(const tsdfs_field *F, const float *o, const float *v
     // ---- first-order pass (ordinary backprop of the forward, with the
     // second-order contributions Z2 injected at every hidden layer):
     // Zbar_l = Hbar_l softplus'(Z_l) (x 1/sqrt2 out of the skip input) + Z2_l
-    BWD(gemm_wgrad(C, R, ny, W, B.Ybar, ldy, B.X[nh], W, gW(nh), W, gb(nh)));
+    BWD(gemm_wgrad(C, R, ny, W, B.Ybar, false, ldy, B.X[nh], sb, W, gW(nh), W, gb(nh)));
     auto fo_epi = [&](int l, float s0, float *Zb) {
         Epi e;
         e.mode = E_FO;
@@ -878,12 +959,13 @@ static int network_backward(const tsdfs_field *F, const float *o, const float *v
         return e;
     };
     float *Zb = B.T0, *Zbn = B.T1;
-    BWD(gemm_row(C, R, W, ny, B.Ybar, ldy, B.Wt[nh], ldt(nh), fo_epi(nh - 1, 1.0f, Zb)));
+    BWD(gemm_row(C, R, W, ny, B.Ybar, false, ldy, B.Wt[nh], ldt(nh), fo_epi(nh - 1, 1.0f, Zb)));
     for (int l = nh - 1; l >= 0; --l) {
         const int in = F->din[l], out = F->dout[l];
-        BWD(gemm_wgrad(C, R, out, in, Zb, W, B.X[l], l == 0 ? ldg : W, gW(l), in, gb(l)));
+        BWD(gemm_wgrad(C, R, out, in, Zb, false, W, B.X[l], sb && l > 0, l == 0 ? ldg : W, gW(l),
+                       in, gb(l)));
         if (l > 0) {
-            BWD(gemm_row(C, R, in, out, Zb, W, B.Wt[l], ldt(l),
+            BWD(gemm_row(C, R, in, out, Zb, false, W, B.Wt[l], ldt(l),
                          fo_epi(l - 1, (l == skip) ? rs2 : 1.0f, Zbn)));
             float *tmp = Zb;
             Zb = Zbn;
