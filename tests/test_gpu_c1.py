@@ -59,11 +59,13 @@ def test_integrate_matches_oracle_and_is_deterministic(c1):
     for rep in range(2):
         st = ops.new_state(grid)
         nup = torch.zeros(1, dtype=torch.int64, device="cuda")
-        # two batches in a different order on the second run
+        # two batches; on the second run three ragged ones (sizes that are
+        # not multiples of the 64-lane wave, so runs of equal voxels meet
+        # wave boundaries elsewhere) in reverse order
         half = o.shape[0] // 2
         order = [(0, half), (half, o.shape[0])]
         if rep:
-            order = order[::-1]
+            order = [(20001, o.shape[0]), (1000, 20001), (0, 1000)]
         for a, bnd in order:
             ops.integrate(grid, st, dev(o[a:bnd]), dev(v[a:bnd]), dev(d[a:bnd]), nup)
         torch.cuda.synchronize()
