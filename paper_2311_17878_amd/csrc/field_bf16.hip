@@ -2,9 +2,12 @@
 // v_mfma_f32_32x32x16_bf16 (FP32 accumulation; bias, activations, encoding,
 // reverse-pass products and outputs in FP32).
 //
-// Layout: a workgroup of 4 waves owns a tile of 128 samples; two workgroups
-// share a compute unit, so one can run its MFMA phase while the other runs
-// its activation (VALU) phase.  Activations live in LDS as BF16,
+// Layout: a group of 4 waves owns a tile of 128 samples; a workgroup holds
+// two groups (one per compute unit), each with its own tile, activations and
+// scratch slot.  Group 1 runs one barrier behind group 0, and every barrier
+// is the whole workgroup's, so the two alternate: while one runs the
+// products of a layer (MFMA), the other runs the activations of its
+// previous one (VALU), on the same SIMDs.  Activations live in LDS as BF16,
 // act[sample][k] (k contiguous, row stride 280 = 35 x 16 B so that the
 // 16-byte B-operand reads of eight consecutive samples hit distinct banks).
 // Each layer Z^T = W H^T is split over the waves by 32-row output tiles
@@ -23,8 +26,9 @@
 
 namespace tsdfs {
 
-constexpr int kBWaves = 4;
-constexpr int kBThreads = kBWaves * 64;
+constexpr int kBWaves = 4;                    // waves of a group
+constexpr int kBThreads = kBWaves * 64;       // threads of a group
+constexpr int kBGroups = kBWGPerCU;           // groups (tiles in flight) per workgroup
 constexpr int kColGroups = kBWaves / 4;       // waves sharing a row pair
 
 typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
@@ -347,26 +351,31 @@ __device__ __forceinline__ void zero_rows(int tid, __bf16 *act, int r0, int r1) 
 }
 
 template <bool FULL>
-__global__ void __launch_bounds__(kBThreads, kBWGPerCU * kBWaves / 4)
+__global__ void __launch_bounds__(kBGroups * kBThreads, kBGroups * kBWaves / 4)
 k_field_bf16(const BPlan P, const float *__restrict__ o, const float *__restrict__ v,
              const float *__restrict__ tval, const int32_t *__restrict__ ray_id, int64_t s_cap,
              const int64_t *__restrict__ s_count, float *__restrict__ f_out,
              float *__restrict__ g_out, float *__restrict__ rgb_out, float *__restrict__ ws) {
-    __shared__ __attribute__((aligned(16))) __bf16 act[kBT * kStride];
-    __shared__ float s_xh[3 * kBT];
-    __shared__ float s_v[3 * kBT];
-    __shared__ float s_g[3 * kBT];
+    __shared__ __attribute__((aligned(16))) __bf16 act_g[kBGroups][kBT * kStride];
+    __shared__ float s_xh_g[kBGroups][3 * kBT];
+    __shared__ float s_v_g[kBGroups][3 * kBT];
+    __shared__ float s_g_g[kBGroups][3 * kBT];
 
-    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    // group gr of the workgroup; wave and thread indices within the group
+    const int wave_wg = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int gr = wave_wg / kBWaves, wave = wave_wg % kBWaves;
+    __bf16 *act = act_g[gr];
+    float *s_xh = s_xh_g[gr], *s_v = s_v_g[gr], *s_g = s_g_g[gr];
     int64_t S = s_cap;
     if (s_count) {
         int64_t c = *s_count;
         S = c < s_cap ? c : s_cap;
     }
     const int64_t n_tiles = (S + kBT - 1) / kBT;
+    const int64_t n_rounds = (n_tiles + kBGroups - 1) / kBGroups;
     // slot: softplus' codes [n_hidden][8][kCB][64][16 B], features
     // [8][kCB][64][32 B], then FP32 eg, gam, jac [64][kBT]
-    float *slot = ws + (size_t)blockIdx.x * bf16_slot_floats(P.n_hidden);
+    float *slot = ws + (size_t)(kBGroups * blockIdx.x + gr) * bf16_slot_floats(P.n_hidden);
     uint4 *scr = (uint4 *)slot;
     float *eg = slot + eg_offset(P.n_hidden);
     float *gam = slot + gam_offset(P.n_hidden);
@@ -374,11 +383,16 @@ k_field_bf16(const BPlan P, const float *__restrict__ o, const float *__restrict
     const float kb = P.kb, c1 = P.c1;
     const int pe = (P.d_gamma - 3) / 6;
 
-    for (int64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
+    // Both groups take every round (a group whose tile lies past the last
+    // one runs it on dead samples: nothing is loaded or stored for samples
+    // >= S), so both execute the same barriers, group 1 shifted by one.
+    if (gr == 1) __syncthreads();
+    for (int64_t round = blockIdx.x; round < n_rounds; round += gridDim.x) {
+        const int64_t tile = kBGroups * round + gr;
         // the thread index is re-derived opaquely per tile so that per-lane
         // addresses are rebuilt where used instead of living (spilled) across
         // the tile loop
-        const int tid = opq((int)threadIdx.x);
+        const int tid = opq((int)threadIdx.x % kBThreads);
         const int lane = tid & 63, col = lane & 31, khalf = lane >> 5;
         const int64_t s0 = tile * kBT;
         if (tid < kBT) {
@@ -573,17 +587,22 @@ k_field_bf16(const BPlan P, const float *__restrict__ o, const float *__restrict
         });
         __syncthreads();
     }
+    if (gr == 0) __syncthreads();
 }
 
+// grid: tiles in flight (one scratch slot each, at most kBWGPerCU per
+// compute unit), taken kBGroups to a workgroup
 int launch_field_bf16(const BPlan &P, int grid, const float *o, const float *v, const float *t,
                       const int32_t *ray_id, int64_t s_cap, const int64_t *s_count, float *f,
                       float *g, float *rgb, float *ws, hipStream_t stream) {
+    static_assert(kBGroups == 2, "one group runs one barrier behind the other");
+    const int blocks = (grid + kBGroups - 1) / kBGroups;
     if (g)
-        hipLaunchKernelGGL(k_field_bf16<true>, dim3(grid), dim3(kBThreads), 0, stream, P, o, v, t,
-                           ray_id, s_cap, s_count, f, g, rgb, ws);
+        hipLaunchKernelGGL(k_field_bf16<true>, dim3(blocks), dim3(kBGroups * kBThreads), 0, stream,
+                           P, o, v, t, ray_id, s_cap, s_count, f, g, rgb, ws);
     else
-        hipLaunchKernelGGL(k_field_bf16<false>, dim3(grid), dim3(kBThreads), 0, stream, P, o, v, t,
-                           ray_id, s_cap, s_count, f, g, rgb, ws);
+        hipLaunchKernelGGL(k_field_bf16<false>, dim3(blocks), dim3(kBGroups * kBThreads), 0,
+                           stream, P, o, v, t, ray_id, s_cap, s_count, f, g, rgb, ws);
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 

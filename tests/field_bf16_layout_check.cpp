@@ -139,7 +139,8 @@ static void check(const Shape &s) {
         CHECK(r0 + dg <= 16 * k16(din[s.skip]), "re-injected encoding rows %d..%d", r0, r0 + dg);
     }
     CHECK(16 * k16(dg) <= kStride, "encoding rows");
-    // LDS of one workgroup: the tile, x_hat, v and grad f (FP32, 3 x kBT each)
+    // LDS of one tile group (kBWGPerCU of them share a compute unit's LDS):
+    // the tile, x_hat, v and grad f (FP32, 3 x kBT each)
     CHECK(act_size * 2 + 3 * 3 * kBT * 4 <= 160 * 1024 / kBWGPerCU, "LDS %d bytes",
           act_size * 2 + 36 * kBT);
 }
