@@ -36,8 +36,8 @@ FIELD_SOURCES = {"k_field_fp32": ["field_fp32.hip", "field_common.hpp", "common.
                  "k_field_bf16": ["field_bf16.hip", "field_bf16_layout.hpp", "field_common.hpp",
                                   "common.hpp", "field.hip"]}
 TRAFFIC = {
-    "k_field_fp32": {"sha256_16": "f3645b604ee31a4d", "fetch_kib": 3.3976e+07, "write_kib": 5.785e+07},
-    "k_field_bf16": {"sha256_16": "f1e8558ce9e0a24d", "fetch_kib": 1.9618e+07, "write_kib": 2.1038e+07},
+    "k_field_fp32": {"sha256_16": "f3645b604ee31a4d", "fetch_kib": 3.4028e+07, "write_kib": 5.7852e+07},
+    "k_field_bf16": {"sha256_16": "25b5b12f71966893", "fetch_kib": 1.3270e+07, "write_kib": 2.1042e+07},
 }
 COPY_SCALE = {"fetch": 2.0, "write": 1.0}
 
