@@ -124,7 +124,7 @@ def cpu_model():
     return None
 
 
-def panorama_leg(steps, warmup):
+def panorama_leg(steps, warmup, tile=8):
     """The large panorama workload in BF16: the 512^3 volume fused from all
     300 views of 512^2 (78.6 M rays), one equirectangular 2048 x 1024 view
     (2.1 M rays, 1 to 64 samples per ray, the ragged samples in one
@@ -137,7 +137,7 @@ def panorama_leg(steps, warmup):
     cfg = get_config("c5")
     g, s = cfg.grid, cfg.sampling
     t0 = time.time()
-    o, v, d = cfg.integration_rays(progress=lambda k, n: log(f"c5 depth maps {k}/{n}"))
+    o, v, d = cfg.integration_rays(progress=lambda k, n: log(f"c5 depth maps {k}/{n}"), tile=tile)
     ro, rv = cfg.render_rays()
     log(f"c5 inputs: {o.shape[0]} training rays, {ro.shape[0]} render rays "
         f"({time.time() - t0:.1f} s)")
@@ -184,7 +184,8 @@ def panorama_leg(steps, warmup):
                     f"h={g.h:.6f} m; networks as the room's; BF16 products, FP32 accumulation",
         "precision": "bf16",
         "integrate": {"rays": n_train, "ms": integ_ms, "rays_per_s": n_train / (integ_ms * 1e-3),
-                      "voxel_updates": int(nup.item())},
+                      "voxel_updates": int(nup.item()),
+                      "ray_order": "8x8 pixel blocks per view" if tile == 8 else "row by row"},
         "ms_per_step": ms, "rays_per_s": n_rays / (ms * 1e-3),
         "samples_per_ray": {"mean": S / n_rays, "min": int(counts.min()),
                             "p50": float(np.percentile(counts, 50)),
@@ -239,9 +240,9 @@ def main():
                     help="fine samples per ray of the coarse + fine leg (0: skip the leg)")
     ap.add_argument("--fill-rounds", type=int, default=2,
                     help="rounds of filling unseen voxels on a copy of the volume (0: skip)")
-    ap.add_argument("--ray-order", default="row", choices=["row", "tile8"],
-                    help="order of the training rays within each view (integration sums do not "
-                         "depend on it)")
+    ap.add_argument("--ray-order", default="tile8", choices=["row", "tile8"],
+                    help="order of the training rays within each view: by 8x8 pixel blocks "
+                         "(default) or row by row; the fused volume is the same bit for bit")
     ap.add_argument("--no-graph", dest="graph", action="store_false",
                     help="skip the recorded-graph leg")
     ap.add_argument("--no-rho-sweep", dest="rho_sweep", action="store_false",
@@ -393,6 +394,7 @@ def main():
             "hbm_GB_per_s": (28 * o.shape[0] + 24 * updates) / (integ_ms * 1e-3) / 1e9,
             "hbm_frac": (28 * o.shape[0] + 24 * updates) / (integ_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
             "finalize_ms": fin_ms,
+            "ray_order": "8x8 pixel blocks per view" if args.ray_order == "tile8" else "row by row",
             "paper_context": "1.445e6 rays/s (0.692 us/ray, 39.0 M rays in 27.02 s, GPU unnamed)",
         },
     }
@@ -551,7 +553,7 @@ def main():
             cfg_n = None
         if cfg_n is not None:
             gn = cfg_n.grid
-            _, _, dn = cfg_n.integration_rays()
+            _, _, dn = cfg_n.integration_rays(tile=8 if args.ray_order == "tile8" else 0)
             dn_d = dev(dn)
             grid_n = ops.make_grid(gn.n, gn.lo, gn.h, gn.d_t, gn.d_s, gn.nb_radius, gn.m_consec)
             Rn = TsdfRenderer(grid_n, field, s.rho_num, s.rho_den, s.n_min, s.n_max, cfg.neus_s,
@@ -827,7 +829,8 @@ def main():
         log(f"hs 64+64: {hs_ms:.2f} ms/step")
 
     if args.c5 and cfg.name in ("c2", "c3", "c4"):
-        result["c5_panorama_bf16"] = panorama_leg(max(3, args.steps // 2), 1)
+        result["c5_panorama_bf16"] = panorama_leg(max(3, args.steps // 2), 1,
+                                                  8 if args.ray_order == "tile8" else 0)
 
     if not args.no_cpu_baseline:
         try:

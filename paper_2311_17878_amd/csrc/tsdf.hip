@@ -229,6 +229,61 @@ __device__ __forceinline__ bool wave_run_tail(int64_t X, int lane) {
     return lane == 63 || Xn != X;
 }
 
+__device__ __forceinline__ int64_t readlane64(int64_t x, int l) {
+    return (int64_t)(((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(x >> 32), l) << 32) |
+                     (uint32_t)__builtin_amdgcn_readlane((int)x, l));
+}
+
+// The lanes with `on` set hold (key X, sum s, count c) (the run tails of a
+// step); lanes with equal keys anywhere in the wave are merged, one key at a
+// time: true on the first lane of each key, which receives the key's total
+// sum and count (the whole wave takes part; the loop runs once per distinct
+// key).  Rays listed by pixel blocks put the same voxel in lanes that are not
+// consecutive (the pixel above), which the runs alone do not merge.  With
+// more than max_on lanes set (fine voxels: mostly distinct keys) the loop
+// would cost more than the atomics it saves, and every lane keeps its own.
+__device__ __forceinline__ bool wave_merge_keys(int64_t X, bool on, int lane, int64_t &s,
+                                                uint32_t &c, int max_on) {
+    uint64_t pend = __ballot(on);
+    if (__popcll(pend) > max_on) return on;
+    bool lead = false;
+    while (pend) {
+        const int ld = __builtin_ctzll(pend);
+        const int64_t key = readlane64(X, ld);
+        const bool mine = ((pend >> lane) & 1ull) && X == key;
+        const uint64_t grp = __ballot(mine);
+        if (grp != (1ull << ld)) {
+            const int64_t ts = wave_scan_add(mine ? s : 0);
+            const int64_t tc = wave_scan_add(mine ? (int64_t)c : 0);
+            const int64_t vs = readlane64(ts, 63);
+            const uint32_t vc = (uint32_t)__builtin_amdgcn_readlane((int)tc, 63);
+            if (lane == ld) {
+                s = vs;
+                c = vc;
+            }
+        }
+        if (lane == ld) lead = true;
+        pend &= ~grp;
+    }
+    return lead;
+}
+
+// the first lane of each distinct key among the lanes with `on` set (each
+// lane its own with more than max_on set)
+__device__ __forceinline__ bool wave_first_of_key(int64_t X, bool on, int lane, int max_on) {
+    uint64_t pend = __ballot(on);
+    if (__popcll(pend) > max_on) return on;
+    bool lead = false;
+    while (pend) {
+        const int ld = __builtin_ctzll(pend);
+        const int64_t key = readlane64(X, ld);
+        const uint64_t grp = __ballot(((pend >> lane) & 1ull) && X == key);
+        if (lane == ld) lead = true;
+        pend &= ~grp;
+    }
+    return lead;
+}
+
 __device__ __forceinline__ void count_updates(int64_t updates, unsigned long long *n_updates) {
     if (!n_updates) return;
     // one atomic per wave
@@ -240,8 +295,10 @@ __device__ __forceinline__ void count_updates(int64_t updates, unsigned long lon
 // Every lane of a wave takes each step together (the shuffles need the
 // whole wave); a finished lane keeps a voxel key of its own and adds
 // nothing.  Lanes on the same voxel in consecutive lanes (neighbouring
-// pixels) add their run's sum and count with one pair of atomics: integer
-// sums, so the totals do not depend on how the updates are grouped.
+// pixels) form runs; the runs' tails on the same voxel anywhere in the wave
+// are merged, and each voxel of a step gets its sum and count with one pair
+// of atomics: integer sums, so the totals do not depend on how the updates
+// are grouped.
 __global__ void __launch_bounds__(256) k_integrate(LatGrid g, int64_t *__restrict__ sum,
                                                    uint32_t *__restrict__ cnt,
                                                    const float *__restrict__ o,
@@ -260,8 +317,9 @@ __global__ void __launch_bounds__(256) k_integrate(LatGrid g, int64_t *__restric
         int64_t rs;
         uint32_t rl;
         const bool tail = wave_run(X, s32, lane, rs, rl);
+        const bool lead = wave_merge_keys(X, up && tail, lane, rs, rl, 64);
         if (up) {
-            if (tail) {
+            if (lead) {
                 atomicAdd((unsigned long long *)&sum[X], (unsigned long long)rs);
                 atomicAdd(&cnt[X], rl);
             }
@@ -308,11 +366,11 @@ __global__ void __launch_bounds__(256) k_sparse_mark(LatGrid g, BrickGrid bg,
         int64_t X = -1 - lane, s32 = 0;
         bool band = false;
         const bool up = int_update(g, q, X, s32, band);
-        const bool tail = wave_run_tail(X, lane);
+        const bool lead = wave_first_of_key(X, up && wave_run_tail(X, lane), lane, 32);
         if (up) {
             const int64_t b = brick_of(bg, q.w.i);
             if (band) band_flag[b] = 1u;
-            if (tail)
+            if (lead)
                 atomicOr(&seen[b * 8 + (q.w.i[2] & 7)],
                          1ull << ((q.w.i[1] & 7) * 8 + (q.w.i[0] & 7)));
             int_advance(g, q);
@@ -341,14 +399,16 @@ __global__ void __launch_bounds__(256) k_sparse_accum(LatGrid g, BrickGrid bg,
         int64_t rs;
         uint32_t rl;
         const bool tail = wave_run(X, s32, lane, rs, rl);
+        // only the tails in band bricks add anything: only they take part
+        int32_t sl = -1;
+        if (up && tail) sl = slot[brick_of(bg, q.w.i)];
+        const bool live = sl >= 0 && sl < cap;
+        const bool lead = wave_merge_keys(X, live, lane, rs, rl, 32);
         if (up) {
-            if (tail) {
-                const int32_t sl = slot[brick_of(bg, q.w.i)];
-                if (sl >= 0 && sl < cap) {
-                    const int64_t e = (int64_t)sl * 512 + local_of(q.w.i);
-                    atomicAdd((unsigned long long *)&psum[e], (unsigned long long)rs);
-                    atomicAdd(&pcnt[e], rl);
-                }
+            if (lead) {
+                const int64_t e = (int64_t)sl * 512 + local_of(q.w.i);
+                atomicAdd((unsigned long long *)&psum[e], (unsigned long long)rs);
+                atomicAdd(&pcnt[e], rl);
             }
             ++updates;
             int_advance(g, q);

@@ -56,22 +56,27 @@ def test_integrate_matches_oracle_and_is_deterministic(c1):
     g, grid = c1["g"], c1["grid"]
     o, v, d = c1["rays"]
     states = []
-    for rep in range(2):
+    # the same rays listed by 8x8 pixel blocks of each view (same volume)
+    ob, vb, db = c1["cfg"].integration_rays(tile=8)
+    for rep in range(3):
         st = ops.new_state(grid)
         nup = torch.zeros(1, dtype=torch.int64, device="cuda")
         # two batches; on the second run three ragged ones (sizes that are
         # not multiples of the 64-lane wave, so runs of equal voxels meet
-        # wave boundaries elsewhere) in reverse order
+        # wave boundaries elsewhere) in reverse order; on the third the
+        # block-ordered rays, where equal voxels sit in lanes 8 apart
         half = o.shape[0] // 2
         order = [(0, half), (half, o.shape[0])]
-        if rep:
+        if rep == 1:
             order = [(20001, o.shape[0]), (1000, 20001), (0, 1000)]
+        oo, vv, dd = (ob, vb, db) if rep == 2 else (o, v, d)
         for a, bnd in order:
-            ops.integrate(grid, st, dev(o[a:bnd]), dev(v[a:bnd]), dev(d[a:bnd]), nup)
+            ops.integrate(grid, st, dev(oo[a:bnd]), dev(vv[a:bnd]), dev(dd[a:bnd]), nup)
         torch.cuda.synchronize()
         states.append(host(st).copy())
         assert int(nup.item()) == c1["st"].updates
     assert np.array_equal(states[0], states[1]), "integration is not order independent"
+    assert np.array_equal(states[0], states[2]), "block-ordered rays give another volume"
     N = g.n_vox
     ssum = states[0][: 8 * N].view(np.int64)
     cnt = states[0][8 * N: 12 * N].view(np.uint32)

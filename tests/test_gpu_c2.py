@@ -33,7 +33,9 @@ def c2():
     from paper_2311_17878_amd.pipeline import TsdfRenderer
     cfg = get_config("c2")
     g, s = cfg.grid, cfg.sampling
-    o, v, d = cfg.integration_rays()
+    # the training rays listed by 8x8 pixel blocks of each view (the volume
+    # does not depend on the order; the stored one came from row order)
+    o, v, d = cfg.integration_rays(tile=8)
     ro, rv = cfg.render_rays()
     grid = ops.make_grid(g.n, g.lo, g.h, g.d_t, g.d_s, g.nb_radius, g.m_consec)
     field = ops.Field(cfg.sdf.width, cfg.sdf.n_hidden, cfg.sdf.pe_freqs, cfg.sdf.skip_at,

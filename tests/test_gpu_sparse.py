@@ -123,7 +123,7 @@ def test_two_level_volume_room():
     holding a voxel whose integer sum is below count x D_T is a band brick."""
     cfg = get_config("c2")
     g = cfg.grid
-    o, v, d = cfg.integration_rays()
+    o, v, d = cfg.integration_rays(tile=8)   # by 8x8 pixel blocks; same volume
     r = build(g, o, v, d)
     gold = np.load(os.path.join(HERE, "golden", "c2_volume.npz"))
     N = int(gold["n_vox"])
