@@ -93,9 +93,12 @@ int tsdf_reset(const tsdfs_grid *grid, void *state, void *stream);
  * voxel receives s, the first voxel with s <= -D_T ends the ray.  A depth
  * that is not finite, <= 0, < 2^-16 m or >= 2^12 m marks a free-space ray
  * (s = +D_T until the grid exit).  Integer atomics make the result
- * independent of ray order.  Accumulates into `state`; call repeatedly for
- * batches.  Optional n_updates_dev: device int64 counter incremented by the
- * number of voxel updates (NULL to skip). */
+ * independent of ray order.  Order still matters for speed: updates of one
+ * voxel by rays handled together (64 consecutive rays) are summed before
+ * the atomics, so rays listed by small pixel blocks of their depth image
+ * (8 x 8) fuse faster than rows of pixels.  Accumulates into `state`; call
+ * repeatedly for batches.  Optional n_updates_dev: device int64 counter
+ * incremented by the number of voxel updates (NULL to skip). */
 int tsdf_integrate(const tsdfs_grid *grid, void *state, const float *o, const float *v,
                    const float *depth, int64_t n_rays, int64_t *n_updates_dev, void *stream);
 
