@@ -147,6 +147,26 @@ __device__ __forceinline__ int exit_axis_reg(const Walk &w) {
     return c2 ? 2 : (c1 ? 1 : 0);
 }
 
+// walk_step with compile-time indices only; also returns the exit parameter
+// (num / den) of the voxel left
+__device__ __forceinline__ bool walk_step_reg(const LatGrid &g, Walk &w, int a, int32_t &ex_num,
+                                              int32_t &ex_den) {
+    bool inside = true;
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+        if (a == b) {
+            ex_num = w.num[b];
+            ex_den = w.den[b];
+            w.en_num = w.num[b];
+            w.en_den = w.den[b];
+            w.i[b] += w.step[b];
+            w.num[b] += (int32_t)g.H;
+            inside = w.i[b] >= 0 && w.i[b] < g.n[b];
+        }
+    }
+    return inside;
+}
+
 __device__ __forceinline__ void int_advance(const LatGrid &g, IntRay &q) {
     const int a = exit_axis_reg(q.w);
     bool inside = true;
@@ -601,35 +621,66 @@ __global__ void __launch_bounds__(256) k_bounds(LatGrid g, const uint8_t *__rest
         int32_t inn, ind, outn, outd;
         Walk w;
         if (grid_range(g, r, inn, ind, outn, outd) && walk_begin(g, r, inn, ind, w)) {
+            // The flags of the next voxel are loaded before the current one is
+            // tested (the walk does not depend on them), so two loads are in
+            // flight per step.  A voxel is visited while its FP32 entry
+            // parameter is below t_far (no division when t_far is infinite).
+            const bool far_limit = !(t_far == INFINITY);   // NaN: no voxel is below it
+            auto before_far = [&](const Walk &x) __attribute__((always_inline)) {
+                return !far_limit || tau_f32(x.en_num, x.en_den) < t_far;
+            };
+            auto flag_of = [&](const Walk &x, bool valid) __attribute__((always_inline)) {
+                return flags[valid ? vox_linear(g, x.i) : 0];   // in bounds either way
+            };
+            Walk cur = w, nxt;
+            bool ok = before_far(cur);
+            uint8_t fc = flag_of(cur, ok);
             // phase 1: first voxel of the surface group
-            bool inside = true, found = false;
-            while (inside && tau_f32(w.en_num, w.en_den) < t_far) {
+            bool found = false;
+            while (ok) {
                 ++steps;
-                if (flags[vox_linear(g, w.i)] & 1u) { found = true; break; }
-                inside = walk_step(g, w, walk_exit_axis(w));
+                nxt = cur;
+                int32_t xn, xd;
+                const bool nok =
+                    walk_step_reg(g, nxt, exit_axis_reg(nxt), xn, xd) && before_far(nxt);
+                const uint8_t fn = flag_of(nxt, nok);
+                if (fc & 1u) {
+                    found = true;
+                    break;
+                }
+                cur = nxt;
+                fc = fn;
+                ok = nok;
             }
             if (found) {
-                fh = (int32_t)vox_linear(g, w.i);
-                tn = tau_f32(w.en_num, w.en_den);
+                fh = (int32_t)vox_linear(g, cur.i);
+                tn = tau_f32(cur.en_num, cur.en_den);
                 st = TSDFS_NO_FAR;
                 int m = 0;
-                float last_exit = tn;
+                int32_t ex_num = cur.en_num, ex_den = cur.en_den;   // exit of the last voxel
                 bool first = true;
-                while (inside && tau_f32(w.en_num, w.en_den) < t_far) {
+                while (ok) {
                     if (!first) ++steps;
                     first = false;
                     ++nv;
-                    m = (flags[vox_linear(g, w.i)] & 2u) ? m + 1 : 0;
-                    int a = walk_exit_axis(w);
-                    last_exit = tau_f32(w.num[a], w.den[a]);
+                    nxt = cur;
+                    const bool nok =
+                        walk_step_reg(g, nxt, exit_axis_reg(nxt), ex_num, ex_den) && before_far(nxt);
+                    const uint8_t fn = flag_of(nxt, nok);
+                    m = (fc & 2u) ? m + 1 : 0;
                     if (m == g.M) {
-                        tf = last_exit;
+                        tf = tau_f32(ex_num, ex_den);
                         st = TSDFS_HIT;
                         break;
                     }
-                    inside = walk_step(g, w, a);
+                    cur = nxt;
+                    fc = fn;
+                    ok = nok;
                 }
-                if (st == TSDFS_NO_FAR) tf = last_exit < t_far ? last_exit : t_far;
+                if (st == TSDFS_NO_FAR) {
+                    const float last_exit = tau_f32(ex_num, ex_den);
+                    tf = last_exit < t_far ? last_exit : t_far;
+                }
             }
         }
     }
