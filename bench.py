@@ -9,8 +9,10 @@ encoding, skip at layer 4, 257 outputs) and colour network 4x256, FP32.
 A timed step is one TSDF-bounded render of the view with the volume resident:
 Alg. 1 bounds -> adaptive placement -> field (SDF + grad f + colour) ->
 compositing.  Also reported on the same GPU: dense 64+64 hierarchical
-sampling, the BF16 field (when supported), the integration throughput, the
-field kernel's roofline fraction and the CPU oracle on a bounded sample.
+sampling, the BF16 field, the field with FP32 operands as three-part BF16
+products (FP32 accuracy on the BF16 matrix cores), the integration
+throughput, the field kernel's roofline fraction and the CPU oracle on a
+bounded sample.
 """
 from __future__ import annotations
 
@@ -33,6 +35,8 @@ HBM_PEAK_GBS = 8000.0
 # the sources whose digest is given; scaled by a plain copy's counters
 # (fetch x 2, write x 1).  Reported only while the sources still match.
 FIELD_SOURCES = {"k_field_fp32": ["field_fp32.hip", "field_common.hpp", "common.hpp", "field.hip"],
+                 "k_field_fp32_split": ["field_fp32.hip", "field_common.hpp", "common.hpp",
+                                        "field.hip"],
                  "k_field_bf16": ["field_bf16.hip", "field_bf16_layout.hpp", "field_common.hpp",
                                   "common.hpp", "field.hip"]}
 TRAFFIC = {
@@ -231,6 +235,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-hs", action="store_true")
     ap.add_argument("--no-other", action="store_true", help="skip the other-precision leg")
+    ap.add_argument("--no-split", dest="split", action="store_false",
+                    help="skip the leg with FP32 operands as three-part BF16 products")
     ap.add_argument("--no-train", action="store_true", help="skip the training-step leg")
     ap.add_argument("--no-table1", action="store_true",
                     help="skip Table 1's counting on the training rays and the NeRF-mode leg")
@@ -505,6 +511,36 @@ def main():
                              "k_field_bf16" if other == _lib.BF16 else "k_field_fp32", cfg.name)},
         }
         log(f"{oname}: {ms_o:.3f} ms/step")
+
+    # ---- FP32 operands as three-part BF16 products (FP32 accuracy on the
+    # BF16 matrix cores: six BF16 products per FP32 product) on the same step
+    if args.split:
+        R.precision = _lib.BF16X6
+        for _ in range(args.warmup):
+            R.render(ro_d, rv_d)
+        ev_x = {}
+        torch.cuda.synchronize()
+        start.record()
+        for _ in range(args.steps):
+            R.render(ro_d, rv_d, events=ev_x)
+        end.record()
+        torch.cuda.synchronize()
+        R.precision = prec
+        ms_x = start.elapsed_time(end) / args.steps
+        field_x = float(np.mean([a.elapsed_time(b) for a, b in ev_x["field"]]))
+        alg_x = S * fl_sample / (field_x * 1e-3) / 1e12
+        field_f32 = field_ms if prec == _lib.FP32 else result.get("f32", {}).get("field_ms")
+        result["f32_bf16x6"] = {
+            "ms_per_step": ms_x, "rays_per_s": n_rays / (ms_x * 1e-3), "field_ms": field_x,
+            "field_speedup_vs_f32": (field_f32 / field_x) if field_f32 else None,
+            "fp32_equivalent_TFLOP_s": alg_x,
+            "roofline": {"kernel": "k_field_fp32 (three-part BF16 products)", "bound": "mfma",
+                         "achieved": 6 * alg_x, "peak": PEAK_TFLOPS["bf16"], "unit": "TFLOP/s",
+                         "frac": 6 * alg_x / PEAK_TFLOPS["bf16"],
+                         "work": "6 BF16 MFMA products per FP32 product",
+                         "traffic": field_traffic_bytes("k_field_fp32_split", cfg.name)},
+        }
+        log(f"f32 as bf16x6: {ms_x:.3f} ms/step, field {field_x:.2f} ms")
 
     # ---- coarse + fine inside the TSDF bound ("Ours (full)"): the adaptive
     # samples as coarse sets (SDF only), n_fine fine points per ray, the field

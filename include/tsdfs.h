@@ -327,7 +327,15 @@ typedef struct {
 
 typedef struct tsdfs_field tsdfs_field;
 
-enum { TSDFS_FP32 = 0, TSDFS_BF16 = 1 };
+/* Precision of the field's matrix products (sdf_mlp_fwd, sdf_mlp_bwd).
+ * TSDFS_FP32: FP32 operands on the FP32 matrix cores.  TSDFS_BF16: operands
+ * rounded to BF16 (nearest even), FP32 accumulation.  TSDFS_BF16X6 (forward
+ * only): FP32 operands, each the exact sum of three BF16 parts, multiplied
+ * on the BF16 matrix cores as the six part products that can reach 2^-24 of
+ * the whole, with FP32 accumulation (the three dropped ones stay below
+ * 2^-26 of it): FP32 accuracy at BF16 matrix-core rates.  Everything outside
+ * the products is FP32 in all three. */
+enum { TSDFS_FP32 = 0, TSDFS_BF16 = 1, TSDFS_BF16X6 = 2 };
 
 int tsdfs_field_create(const tsdfs_field_desc *desc, const float *sdf_params_host,
                        const float *color_params_host, tsdfs_field **out);
@@ -337,8 +345,8 @@ int tsdfs_field_destroy(tsdfs_field *field);
  * plain parameters (the SDF block of *n_sdf floats, then the colour block of
  * *n_color, in the layouts tsdfs_field_create takes), owned by the field and
  * updated in place by the caller (e.g. adam_step).  tsdfs_field_repack then
- * rebuilds the packed copies the forward kernels read (FP32 and BF16 MFMA
- * operands, bias tiles) from them on `stream`; tsdfs_field_create packs the
+ * rebuilds the packed copies the forward kernels read (FP32, BF16 and
+ * three-part BF16 MFMA operands, bias tiles) from them on `stream`; tsdfs_field_create packs the
  * same way.  The backward (sdf_mlp_bwd) reads the plain parameters directly. */
 int tsdfs_field_params(tsdfs_field *field, float **params_dev, size_t *n_sdf, size_t *n_color);
 int tsdfs_field_repack(tsdfs_field *field, void *stream);
@@ -353,8 +361,10 @@ int adam_step(float *params, const float *grad, float *m, float *v, int64_t n, f
 /* Evaluate the field at p = o[ray_id] + t v[ray_id] for min(*s_count_dev,
  * s_cap) samples (s_count_dev may be NULL: s_cap samples).  Outputs [S]:
  * f (metres), grad_f [S,3] and rgb [S,3]; with grad_f == rgb == NULL only f
- * is computed (SDF forward only).  precision: TSDFS_FP32 or TSDFS_BF16
- * (BF16 GEMM inputs, FP32 accumulation; everything else FP32).
+ * is computed (SDF forward only).  precision: TSDFS_FP32, TSDFS_BF16
+ * (BF16 GEMM inputs, FP32 accumulation; everything else FP32) or
+ * TSDFS_BF16X6 (FP32 operands as three-part BF16 products); other values:
+ * TSDFS_EUNSUPPORTED.
  * ws: sdf_mlp_fwd_ws_bytes. */
 int sdf_mlp_fwd_ws_bytes(const tsdfs_field *field, size_t *bytes);
 int sdf_mlp_fwd(const tsdfs_field *field, const float *o, const float *v, const float *t,
@@ -406,7 +416,8 @@ int composite(const int32_t *offsets, int64_t n_rays, const float *v, const floa
  * sdf_mlp_fwd).  d_f, d_grad_f may be NULL (zero).  eik_loss (optional,
  * device float) receives the eikonal term.  precision: TSDFS_FP32, or
  * TSDFS_BF16 (every matrix product takes BF16-rounded inputs with FP32
- * accumulation; elementwise work, bias sums and outputs stay FP32).  Every
+ * accumulation; elementwise work, bias sums and outputs stay FP32); other
+ * values (TSDFS_BF16X6 included): TSDFS_EUNSUPPORTED.  Every
  * product runs in the library's own MFMA kernels; the weight gradients and
  * the bias and loss sums reduce over the rows in a fixed order, so repeated
  * calls give identical bits.  No allocation.

@@ -16,7 +16,7 @@ P = c_void_p
 
 TSDFS_OK, TSDFS_EINVAL, TSDFS_ECAPACITY, TSDFS_EHIP, TSDFS_EUNSUPPORTED = 0, -1, -2, -3, -4
 HIT, NO_FAR, MISS, INVALID = 0, 1, 2, 3
-FP32, BF16 = 0, 1
+FP32, BF16, BF16X6 = 0, 1, 2
 
 
 class TsdfsError(RuntimeError):

@@ -73,23 +73,44 @@ __device__ __forceinline__ float src_value(const float *P, const Src &e) {
     return v * e.s;
 }
 
+// The three-part block: element i of its plan (BF16 lane order, one
+// 512-element block per tile and K-step) becomes hi, mid and lo at offsets
+// 0, 512 and 1024 of that block's three-block group.  hi is the nearest-even
+// BF16 of w, mid that of w - hi, lo that of w - hi - mid; both differences
+// are exact in FP32 (each operand is within a factor of two of the value it
+// is subtracted from), and what is left for lo has at most eight significant
+// bits, so w = hi + mid + lo exactly.
 __global__ void k_repack(const float *__restrict__ P, const Src *__restrict__ pf, int64_t nf,
                          float *__restrict__ df, const Src *__restrict__ pb, int64_t nb,
-                         uint16_t *__restrict__ db) {
+                         uint16_t *__restrict__ db, const Src *__restrict__ p3, int64_t n3,
+                         uint16_t *__restrict__ d3) {
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i < nf) df[i] = src_value(P, pf[i]);
     if (i < nb) {
         const __bf16 h = (__bf16)src_value(P, pb[i]);   // round to nearest even
         db[i] = __builtin_bit_cast(uint16_t, h);
     }
+    if (i < n3) {
+        const float w = src_value(P, p3[i]);
+        const __bf16 hi = (__bf16)w;
+        const float r = w - (float)hi;
+        const __bf16 mid = (__bf16)r;
+        const __bf16 lo = (__bf16)(r - (float)mid);
+        uint16_t *o = d3 + (i >> 9) * 1536 + (i & 511);
+        o[0] = __builtin_bit_cast(uint16_t, hi);
+        o[512] = __builtin_bit_cast(uint16_t, mid);
+        o[1024] = __builtin_bit_cast(uint16_t, lo);
+    }
 }
 
 int repack(const tsdfs_field *F, hipStream_t st) {
-    const int64_t n = F->n_pf > F->n_pb ? F->n_pf : F->n_pb;
+    int64_t n = F->n_pf > F->n_pb ? F->n_pf : F->n_pb;
+    if ((int64_t)F->n_p3 > n) n = F->n_p3;
     if (n == 0) return 0;
     hipLaunchKernelGGL(k_repack, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st,
                        F->params_sdf, (const Src *)F->plan_f, (int64_t)F->n_pf, F->dev,
-                       (const Src *)F->plan_b, (int64_t)F->n_pb, F->devb);
+                       (const Src *)F->plan_b, (int64_t)F->n_pb, F->devb,
+                       (const Src *)F->plan_3, (int64_t)F->n_p3, F->dev3);
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
@@ -178,13 +199,13 @@ int tsdfs_field_create(const tsdfs_field_desc *d, const float *sdf_params,
     // Every layer of both plans as a source view m(r, k) -> Src over the
     // plain parameters; bscale multiplies the BF16 copy only.  Offsets into
     // the packed blocks are resolved to device pointers after allocation.
-    std::vector<Src> pf, pb;
-    struct Ref { Layer *L; BLayer *B; size_t w, wb, b; bool has_b; };
+    std::vector<Src> pf, pb, p3;
+    struct Ref { Layer *L; BLayer *B; size_t w, wb, w3, b; bool has_b; };
     std::vector<Ref> refs;
     auto add = [&](Layer *L, BLayer *B, int n_out, int K, auto m, bool has_bias, auto bias,
                    float bscale) {
         L->K8 = round8(K);
-        B->K16 = (K + 15) / 16;
+        L->K16 = B->K16 = (K + 15) / 16;
         L->n_tiles = B->n_tiles = (n_out + 31) / 32;
         L->n_out = B->n_out = n_out;
         size_t w = pf.size();
@@ -195,9 +216,11 @@ int tsdfs_field_create(const tsdfs_field_desc *d, const float *sdf_params,
             e.s *= bscale;
             return e;
         });
+        size_t w3 = p3.size();
+        pack_a_bf16(p3, n_out, K, m);
         size_t b = pf.size();
         if (has_bias) pack_bias(pf, bias, n_out);
-        refs.push_back({L, B, w, wb, b, has_bias});
+        refs.push_back({L, B, w, wb, w3, b, has_bias});
     };
     auto src = [](int64_t a, int64_t b, float sc) { return Src{(int32_t)a, (int32_t)b, sc}; };
     const int32_t none = -1;
@@ -245,25 +268,30 @@ int tsdfs_field_create(const tsdfs_field_desc *d, const float *sdf_params,
             [=](int r) { return src(bl + r, none, 1.0f); }, 1.0f);
     }
 
-    // device blocks: packed FP32, then packed BF16 (256-byte aligned); the
-    // plain parameters; the two gather plans
+    // device blocks: packed FP32, packed BF16, three-part BF16 (each
+    // 256-byte aligned); the plain parameters; the three gather plans
     const size_t fbytes = (pf.size() * sizeof(float) + 255) / 256 * 256;
-    const size_t bbytes = pb.size() * sizeof(uint16_t);
-    hipError_t e = hipMalloc((void **)&F->dev, fbytes + bbytes);
+    const size_t bbytes = (pb.size() * sizeof(uint16_t) + 255) / 256 * 256;
+    const size_t tbytes = 3 * p3.size() * sizeof(uint16_t);
+    hipError_t e = hipMalloc((void **)&F->dev, fbytes + bbytes + tbytes);
     if (e == hipSuccess) e = hipMalloc((void **)&F->params_sdf, (F->n_sdf + F->n_col) * sizeof(float));
-    if (e == hipSuccess) e = hipMalloc(&F->plan_f, (pf.size() + pb.size()) * sizeof(Src));
+    if (e == hipSuccess) e = hipMalloc(&F->plan_f, (pf.size() + pb.size() + p3.size()) * sizeof(Src));
     if (e == hipSuccess) {
         F->devb = (uint16_t *)((char *)F->dev + fbytes);
+        F->dev3 = (uint16_t *)((char *)F->dev + fbytes + bbytes);
         F->params_col = F->params_sdf + F->n_sdf;
         F->plan_b = (Src *)F->plan_f + pf.size();
+        F->plan_3 = (Src *)F->plan_b + pb.size();
         F->n_pf = pf.size();
         F->n_pb = pb.size();
+        F->n_p3 = p3.size();
         e = hipMemcpy(F->params_sdf, sdf_params, F->n_sdf * sizeof(float), hipMemcpyHostToDevice);
     }
     if (e == hipSuccess)
         e = hipMemcpy(F->params_col, color_params, F->n_col * sizeof(float), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(F->plan_f, pf.data(), pf.size() * sizeof(Src), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(F->plan_b, pb.data(), pb.size() * sizeof(Src), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(F->plan_3, p3.data(), p3.size() * sizeof(Src), hipMemcpyHostToDevice);
     if (e == hipSuccess && repack(F, nullptr) != 0) e = hipErrorLaunchFailure;
     if (e == hipSuccess) e = hipStreamSynchronize(nullptr);
     if (e != hipSuccess) {
@@ -277,12 +305,14 @@ int tsdfs_field_create(const tsdfs_field_desc *d, const float *sdf_params,
     for (auto &r : refs) {
         r.L->W = F->dev + r.w;
         r.B->W = (const bf16x8 *)(F->devb + r.wb);
+        r.L->W3 = (const bf16x8 *)(F->dev3 + 3 * r.w3);
         r.L->b = r.B->b = r.has_b ? F->dev + r.b : nullptr;
     }
     // the output layer as two views: the feature tiles, then the f tile
     const int nft = nf / 32;
     P.fout = P.feat;
     P.fout.W = P.feat.W + (size_t)nft * (P.feat.K8 / 8) * 64 * 4;
+    P.fout.W3 = P.feat.W3 + (size_t)nft * P.feat.K16 * 3 * 64;
     P.fout.b = P.feat.b + (size_t)nft * 32;
     P.fout.n_tiles = 1;
     P.fout.n_out = 1;
@@ -345,7 +375,7 @@ int sdf_mlp_fwd(const tsdfs_field *F, const float *o, const float *v, const floa
     TSDFS_CHECK_ARG(F != nullptr, "field is NULL");
     TSDFS_CHECK_ARG(s_cap >= 0, "s_cap must be >= 0");
     TSDFS_CHECK_ARG((grad_f == nullptr) == (rgb == nullptr), "grad_f and rgb must both be set or both NULL");
-    if (precision != TSDFS_FP32 && precision != TSDFS_BF16) {
+    if (precision != TSDFS_FP32 && precision != TSDFS_BF16 && precision != TSDFS_BF16X6) {
         set_error("precision %d not supported", precision);
         return TSDFS_EUNSUPPORTED;
     }
@@ -364,7 +394,7 @@ int sdf_mlp_fwd(const tsdfs_field *F, const float *o, const float *v, const floa
                           (float *)ws, as_stream(stream));
     else
         launch_field_fp32(F->plan, grid, o, v, t, ray_id, s_cap, s_count_dev, f, grad_f, rgb,
-                          (float *)ws, as_stream(stream));
+                          (float *)ws, precision == TSDFS_BF16X6, as_stream(stream));
     TSDFS_LAUNCH_CHECK();
     return TSDFS_OK;
 }

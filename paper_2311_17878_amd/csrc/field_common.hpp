@@ -31,11 +31,16 @@ __host__ __device__ constexpr size_t bf16_slot_floats(int n_hidden) {
 }
 
 // FP32 A operand of v_mfma_f32_32x32x2_f32, packed [n_tiles][K8/8][64 lanes][4]
-// (lane l, element j of group g: row l%32, column 2 (4g + j) + l/32).
+// (lane l, element j of group g: row l%32, column 2 (4g + j) + l/32).  W3
+// holds the same matrix as three BF16 parts w = hi + mid + lo (exact), as
+// A operands of v_mfma_f32_32x32x16_bf16, [n_tiles][K16][part][64 lanes] x 8
+// (the lane order of BLayer), for the split-product form of the kernel.
 struct Layer {
     const float *W;
     const float *b;    // bias [n_tiles*32] (zero padded), or NULL
+    const bf16x8 *W3;  // three-part BF16 copy
     int K8;            // K rounded up to a multiple of 8
+    int K16;           // K / 16, rounded up
     int n_tiles;       // ceil(n_out / 32)
     int n_out;
 };
@@ -82,9 +87,10 @@ int repack(const tsdfs_field *F, hipStream_t stream);
 int launch_field_bf16(const BPlan &P, int grid, const float *o, const float *v, const float *t,
                       const int32_t *ray_id, int64_t s_cap, const int64_t *s_count, float *f,
                       float *g, float *rgb, float *ws, hipStream_t stream);
+// split: the products on the BF16 matrix cores from three-part operands
 int launch_field_fp32(const Plan &P, int grid, const float *o, const float *v, const float *t,
                       const int32_t *ray_id, int64_t s_cap, const int64_t *s_count, float *f,
-                      float *g, float *rgb, float *ws, hipStream_t stream);
+                      float *g, float *rgb, float *ws, bool split, hipStream_t stream);
 
 }  // namespace tsdfs
 
@@ -92,11 +98,13 @@ struct tsdfs_field {
     tsdfs_field_desc desc;
     tsdfs::Plan plan;
     tsdfs::BPlan bplan;
-    float *dev = nullptr;        // all packed weights (FP32 + BF16 blocks)
+    float *dev = nullptr;        // all packed weights (FP32, BF16, three-part BF16 blocks)
     uint16_t *devb = nullptr;    // the BF16 block inside dev
-    void *plan_f = nullptr;      // gather plans of the FP32 and BF16 blocks
-    void *plan_b = nullptr;      //   (one allocation, plan_b after plan_f)
-    size_t n_pf = 0, n_pb = 0;
+    uint16_t *dev3 = nullptr;    // the three-part BF16 block inside dev
+    void *plan_f = nullptr;      // gather plans of the FP32, BF16 and three-part
+    void *plan_b = nullptr;      //   blocks (one allocation, in that order)
+    void *plan_3 = nullptr;
+    size_t n_pf = 0, n_pb = 0, n_p3 = 0;
     int n_wg = 0;                // compute units
     // plain row-major FP32 parameters (host layout) for the backward pass
     float *params_sdf = nullptr, *params_col = nullptr;

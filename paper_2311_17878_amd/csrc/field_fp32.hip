@@ -20,14 +20,15 @@ namespace tsdfs {
 constexpr int kFWaves = 8;
 constexpr int kFThreads = kFWaves * 64;
 
-// Share of one layer for one wave: row tile t0 (< 0: none), column blocks
-// c0 .. c0 + nc - 1.
+// Share of one layer for one wave: row tile t0 (< 0: none) and t1 (< 0:
+// none), column blocks c0 .. c0 + nc - 1.
 struct FSplit {
-    int t0, c0, nc;
+    int t0, t1, c0, nc;
 };
 
 __device__ __forceinline__ FSplit fsplit(int n_t, int wave) {
     FSplit s;
+    s.t1 = -1;
     if (n_t >= 5) {
         s.t0 = wave < n_t ? wave : -1;
         s.c0 = 0;
@@ -45,6 +46,21 @@ __device__ __forceinline__ FSplit fsplit(int n_t, int wave) {
         s.c0 = wave & 3;
         s.nc = 1;
     }
+    return s;
+}
+
+// The split-product form's share: layers of more than four row tiles go to
+// the waves as row tiles (wave % 4, + 4) x column-block pairs (wave / 4), so
+// that each B value split on the VALU feeds two row tiles; smaller layers as
+// in fsplit.
+__device__ __forceinline__ FSplit fsplit_s(int n_t, int wave) {
+    if (n_t < 5) return fsplit(n_t, wave);
+    FSplit s;
+    const int rp = wave & 3;
+    s.t0 = rp;
+    s.t1 = rp + 4 < n_t ? rp + 4 : -1;
+    s.c0 = 2 * (wave >> 2);
+    s.nc = 2;
     return s;
 }
 
@@ -131,36 +147,181 @@ __device__ __forceinline__ void gemm_f(const Layer &L, const float *act, floatx1
     if (g + 1 < G) mma(a2, b2);
 }
 
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef float floatx2 __attribute__((ext_vector_type(2)));
+
+// Two FP32 values as three BF16 parts each, x = hi + mid + lo exactly (one
+// 32-bit word of each part's operand): hi is the nearest-even BF16 of x, mid
+// that of x - hi, lo that of x - hi - mid; both differences are exact (each
+// operand is within a factor of two of the value it is subtracted from) and
+// leave at most eight significant bits for lo.
+__device__ __forceinline__ void split_pair(float x0, float x1, uint32_t &h, uint32_t &m,
+                                           uint32_t &l) {
+    const floatx2 v = {x0, x1};
+    const bf16x2 a = __builtin_convertvector(v, bf16x2);
+    const floatx2 r = v - __builtin_convertvector(a, floatx2);
+    const bf16x2 b = __builtin_convertvector(r, bf16x2);
+    const floatx2 r2 = r - __builtin_convertvector(b, floatx2);
+    const bf16x2 c = __builtin_convertvector(r2, bf16x2);
+    h = __builtin_bit_cast(uint32_t, a);
+    m = __builtin_bit_cast(uint32_t, b);
+    l = __builtin_bit_cast(uint32_t, c);
+}
+
+__device__ __forceinline__ bf16x8 as_bf16x8(const uint32_t (&w)[4]) {
+    return __builtin_bit_cast(bf16x8, make_uint4(w[0], w[1], w[2], w[3]));
+}
+
+// The product of gemm_f on v_mfma_f32_32x32x16_bf16 with both operands in
+// three BF16 parts (weights pre-split in W3, activations split from the FP32
+// act rows per K-step of 16): per step the six part products that can reach
+// 2^-24 of the whole, smallest first (lo.hi, hi.lo, mid.mid, mid.hi,
+// hi.mid, hi.hi); the dropped mid.lo, lo.mid and lo.lo stay below 2^-26 of
+// it.  Every part product is exact in the FP32 accumulator.  Software
+// pipelined: the split of step k + 1 (VALU, one pair of values at a time) is
+// interleaved in program order with the products of step k (MFMA), its B
+// values loaded just before; the A parts of step k + 2 load after the
+// products of step k (two register slots; refills past the last step re-read
+// it).
+template <int NT, int NC>
+__device__ __forceinline__ void gemm_s(const Layer &L, const float *act, floatx16 (&acc)[NT][NC],
+                                       const FSplit &s, int lane) {
+    constexpr int kMf = 6 * NT * NC, kPairs = 4 * NC;
+    const int col = lane & 31, khalf = lane >> 5;
+    const int K16 = L.K16, last = K16 - 1;
+    const bf16x8 *W = L.W3;
+    unsigned ao[NT];
+    ao[0] = (unsigned)opq(s.t0 * K16 * 192 + lane);
+    if (NT == 2) ao[NT - 1] = (unsigned)opq(s.t1 * K16 * 192 + lane);
+    const float *bp = act + 8 * khalf * kTile + s.c0 * 32 + col;
+    bf16x8 a0[NT][3], a1[NT][3];
+    uint32_t h0[NC][4], m0[NC][4], l0[NC][4], h1[NC][4], m1[NC][4], l1[NC][4];
+    float x[8][NC];
+    auto loadA = [&](bf16x8 (&a)[NT][3], int k) __attribute__((always_inline)) {
+#pragma unroll
+        for (int tt = 0; tt < NT; ++tt)
+#pragma unroll
+            for (int p = 0; p < 3; ++p) a[tt][p] = W[ao[tt] + (unsigned)(3 * k + p) * 64u];
+    };
+    auto loadB = [&](int k) __attribute__((always_inline)) {
+#pragma unroll
+        for (int e = 0; e < 8; ++e)
+#pragma unroll
+            for (int j = 0; j < NC; ++j) x[e][j] = bp[(16 * k + e) * kTile + j * 32];
+    };
+    // MFMA i of a step: product i / (NT NC) (lo.hi, hi.lo, mid.mid, mid.hi,
+    // hi.mid, hi.hi) of row tile (i / NC) % NT and column block i % NC
+    auto mfma_i = [&](int i, const bf16x8 (&a)[NT][3], const uint32_t (&h)[NC][4],
+                      const uint32_t (&m)[NC][4], const uint32_t (&l)[NC][4])
+        __attribute__((always_inline)) {
+        const int p = i / (NT * NC), tt = (i / NC) % NT, j = i % NC;
+        const bf16x8 &ai = p == 0 ? a[tt][2] : (p == 1 || p == 4 || p == 5) ? a[tt][0] : a[tt][1];
+        const uint32_t (&bi)[4] = (p == 0 || p == 3 || p == 5) ? h[j] : (p == 1 ? l[j] : m[j]);
+        acc[tt][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ai, as_bf16x8(bi), acc[tt][j], 0, 0, 0);
+    };
+    // pair q of column block j: values k = 2q, 2q + 1 of this lane
+    auto pair_i = [&](int i, uint32_t (&h)[NC][4], uint32_t (&m)[NC][4], uint32_t (&l)[NC][4])
+        __attribute__((always_inline)) {
+        const int j = i / 4, q = i % 4;
+        split_pair(x[2 * q][j], x[2 * q + 1][j], h[j][q], m[j][q], l[j][q]);
+    };
+    // the products of one step with the split of the next: pair split i
+    // follows MFMA 2 + i (kMf - 3) / kPairs, so the B values loaded just
+    // before the step have two MFMAs' time to arrive
+    auto mma_split = [&](const bf16x8 (&a)[NT][3], const uint32_t (&h)[NC][4],
+                         const uint32_t (&m)[NC][4], const uint32_t (&l)[NC][4],
+                         uint32_t (&hn)[NC][4], uint32_t (&mn)[NC][4], uint32_t (&ln)[NC][4])
+        __attribute__((always_inline)) {
+#pragma unroll
+        for (int i = 0; i < kMf; ++i) {
+            mfma_i(i, a, h, m, l);
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int q = 0; q < kPairs; ++q) {
+                if (2 + q * (kMf - 3) / kPairs == i) {
+                    pair_i(q, hn, mn, ln);
+                    __builtin_amdgcn_sched_barrier(0);
+                }
+            }
+        }
+    };
+#pragma unroll
+    for (int tt = 0; tt < NT; ++tt) {
+        const floatx16 bias = fbias_acc(L.b, tt ? s.t1 : s.t0, khalf);
+#pragma unroll
+        for (int j = 0; j < NC; ++j) acc[tt][j] = bias;
+    }
+    loadA(a0, 0);
+    loadA(a1, min(1, last));
+    loadB(0);
+#pragma unroll
+    for (int q = 0; q < kPairs; ++q) pair_i(q, h0, m0, l0);
+    __builtin_amdgcn_sched_barrier(0);
+    loadB(min(1, last));
+    int k = 0;
+    for (; k + 1 < K16; k += 2) {
+        __builtin_amdgcn_sched_barrier(0);
+        mma_split(a0, h0, m0, l0, h1, m1, l1);      // step k; split k + 1
+        loadB(min(k + 2, last));
+        loadA(a0, min(k + 2, last));
+        __builtin_amdgcn_sched_barrier(0);
+        mma_split(a1, h1, m1, l1, h0, m0, l0);      // step k + 1; split k + 2
+        loadB(min(k + 3, last));
+        loadA(a1, min(k + 3, last));
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    if (k < K16) {
+#pragma unroll
+        for (int i = 0; i < kMf; ++i) mfma_i(i, a0, h0, m0, l0);
+    }
+}
+
 // One layer: this wave's share of the product; pre(t, c, buf) for each
 // block (loads the epilogue needs, issued before the barrier); a workgroup
 // barrier when the epilogue overwrites the activations the product reads;
-// then epi(acc, t, c, buf) on each 32x32 block.
-template <int NC, class Pre, class Epi>
+// then epi(acc, t, c, buf) on each 32x32 block.  SPLIT: the product in
+// three-part BF16 (gemm_s), else in FP32 (gemm_f).
+template <bool SPLIT, int NT, int NC, class Pre, class Epi>
 __device__ __forceinline__ void flayer_t(const Layer &L, const float *act, const FSplit &s,
                                          int lane, bool sync, Pre &pre, Epi &epi) {
-    floatx16 acc[NC];
-    gemm_f<NC>(L, act, acc, s, lane);
-    float4 buf[NC][4];
+    floatx16 acc[NT][NC];
+    if constexpr (SPLIT)
+        gemm_s<NT, NC>(L, act, acc, s, lane);
+    else
+        gemm_f<NC>(L, act, acc[0], s, lane);
+    float4 buf[NT][NC][4];
 #pragma unroll
-    for (int j = 0; j < NC; ++j) pre(s.t0, s.c0 + j, buf[j]);
+    for (int tt = 0; tt < NT; ++tt)
+#pragma unroll
+        for (int j = 0; j < NC; ++j) pre(tt ? s.t1 : s.t0, s.c0 + j, buf[tt][j]);
     if (sync) __syncthreads();
 #pragma unroll
-    for (int j = 0; j < NC; ++j) epi(acc[j], s.t0, s.c0 + j, buf[j]);
+    for (int tt = 0; tt < NT; ++tt)
+#pragma unroll
+        for (int j = 0; j < NC; ++j) epi(acc[tt][j], tt ? s.t1 : s.t0, s.c0 + j, buf[tt][j]);
 }
 
-template <class Pre, class Epi>
+template <bool SPLIT, class Pre, class Epi>
 __device__ __forceinline__ void frun_layer(const Layer &L, const float *act, int wave, int lane,
                                            bool sync, Pre pre, Epi epi) {
-    const FSplit s = fsplit(L.n_tiles, wave);
+    const FSplit s = SPLIT ? fsplit_s(L.n_tiles, wave) : fsplit(L.n_tiles, wave);
     if (s.t0 < 0) {
         if (sync) __syncthreads();
+    } else if (SPLIT && s.t1 >= 0) {
+        flayer_t<SPLIT, 2, 2>(L, act, s, lane, sync, pre, epi);
     } else if (s.nc == 4) {
-        flayer_t<4>(L, act, s, lane, sync, pre, epi);
+        flayer_t<SPLIT, 1, 4>(L, act, s, lane, sync, pre, epi);
     } else if (s.nc == 2) {
-        flayer_t<2>(L, act, s, lane, sync, pre, epi);
+        flayer_t<SPLIT, 1, 2>(L, act, s, lane, sync, pre, epi);
     } else {
-        flayer_t<1>(L, act, s, lane, sync, pre, epi);
+        flayer_t<SPLIT, 1, 1>(L, act, s, lane, sync, pre, epi);
     }
+}
+
+// rows of act a layer's product reads: K padded to its K-step
+template <bool SPLIT>
+__device__ __forceinline__ int kpad(const Layer &L) {
+    return SPLIT ? 16 * L.K16 : L.K8;
 }
 
 // ld(t, c, buf) for every block of the share, then use(t, c, buf).
@@ -275,7 +436,7 @@ __device__ __forceinline__ void fgamma_grad_reduce(int tid, const float *eg, con
     s_g[a * kTile + c] += sum;
 }
 
-template <bool FULL>
+template <bool FULL, bool SPLIT>
 __global__ void __launch_bounds__(kFThreads, 1)
 k_field_fp32(const Plan P, const float *__restrict__ o, const float *__restrict__ v,
              const float *__restrict__ tval, const int32_t *__restrict__ ray_id, int64_t s_cap,
@@ -330,12 +491,12 @@ k_field_fp32(const Plan P, const float *__restrict__ o, const float *__restrict_
             }
         }
         __syncthreads();
-        fencode_tile(tid, s_xh, pe, gam, jac, act, P.fwd[0].K8);
+        fencode_tile(tid, s_xh, pe, gam, jac, act, kpad<SPLIT>(P.fwd[0]));
         __syncthreads();
         auto no_pre = [](int, int, float4 (&)[4]) __attribute__((always_inline)) {};
         // ---- SDF hidden layers: h = softplus(z) -> act, softplus'(z) -> scratch
         for (int l = 0; l < P.n_hidden; ++l) {
-            frun_layer(P.fwd[l], act, wave, lane, true, no_pre,
+            frun_layer<SPLIT>(P.fwd[l], act, wave, lane, true, no_pre,
                        [&](floatx16 &a, int t, int c, const float4 (&)[4]) __attribute__((always_inline)) {
                 const int cc = c * 32 + col;
                 floatx16 h, d;
@@ -360,14 +521,14 @@ k_field_fp32(const Plan P, const float *__restrict__ o, const float *__restrict_
                 __syncthreads();
                 const int r = P.fwd[l].n_out;
                 finject_gamma(tid, act, r, P.d_gamma, gam);
-                for (int idx = tid + (r + P.d_gamma) * kTile; idx < P.fwd[l + 1].K8 * kTile;
+                for (int idx = tid + (r + P.d_gamma) * kTile; idx < kpad<SPLIT>(P.fwd[l + 1]) * kTile;
                      idx += kFThreads)
                     act[idx] = 0.0f;
             }
             __syncthreads();
         }
         // ---- output layer: the f tile, and the features -> scratch
-        frun_layer(P.fout, act, wave, lane, false, no_pre,
+        frun_layer<SPLIT>(P.fout, act, wave, lane, false, no_pre,
                    [&](floatx16 &a, int t, int c, const float4 (&)[4]) __attribute__((always_inline)) {
             if (khalf == 0) {
                 int64_t s = s0 + c * 32 + col;
@@ -378,7 +539,7 @@ k_field_fp32(const Plan P, const float *__restrict__ o, const float *__restrict_
             __syncthreads();
             continue;
         }
-        frun_layer(P.feat, act, wave, lane, false, no_pre,
+        frun_layer<SPLIT>(P.feat, act, wave, lane, false, no_pre,
                    [&](floatx16 &a, int t, int c, const float4 (&)[4]) __attribute__((always_inline)) {
             float4 *so = scr + opq(fsc(P.n_hidden, t, c, lane));
 #pragma unroll
@@ -415,7 +576,7 @@ k_field_fp32(const Plan P, const float *__restrict__ o, const float *__restrict_
         for (int l = P.n_hidden - 1; l >= 0; --l) {
             const int n_prev = l > 0 ? P.fwd[l - 1].n_out : 0;
             const int sp_tiles = l > 0 ? P.fwd[l - 1].n_tiles : 0;
-            frun_layer(P.bwd[l], act, wave, lane, true,
+            frun_layer<SPLIT>(P.bwd[l], act, wave, lane, true,
                        [&](int t, int c, float4 (&b)[4]) __attribute__((always_inline)) {
                            // tiles past the previous layer's outputs take
                            // softplus' = 0 (the load stays in bounds)
@@ -470,12 +631,12 @@ k_field_fp32(const Plan P, const float *__restrict__ o, const float *__restrict_
             act[(P.n_feat + j) * kTile + c] =
                 j < 3 ? s_xh[j * kTile + c] : (j < 6 ? s_v[(j - 3) * kTile + c] : s_g[(j - 6) * kTile + c]);
         }
-        for (int idx = tid + (P.n_feat + 9) * kTile; idx < P.col[0].K8 * kTile; idx += kFThreads)
+        for (int idx = tid + (P.n_feat + 9) * kTile; idx < kpad<SPLIT>(P.col[0]) * kTile; idx += kFThreads)
             act[idx] = 0.0f;
         __syncthreads();
         // ---- colour hidden layers (ReLU)
         for (int l = 0; l < P.col_hidden; ++l) {
-            frun_layer(P.col[l], act, wave, lane, true, no_pre,
+            frun_layer<SPLIT>(P.col[l], act, wave, lane, true, no_pre,
                        [&](floatx16 &a, int t, int c, const float4 (&)[4]) __attribute__((always_inline)) {
                 floatx16 h;
 #pragma unroll
@@ -485,7 +646,7 @@ k_field_fp32(const Plan P, const float *__restrict__ o, const float *__restrict_
             __syncthreads();
         }
         // ---- rgb = sigmoid(W h + b): rows 0..2 of one tile, lanes 0..31
-        frun_layer(P.rgb, act, wave, lane, false, no_pre,
+        frun_layer<SPLIT>(P.rgb, act, wave, lane, false, no_pre,
                    [&](floatx16 &a, int t, int c, const float4 (&)[4]) __attribute__((always_inline)) {
             if (khalf == 0) {
                 int64_t s = s0 + c * 32 + col;
@@ -501,13 +662,11 @@ k_field_fp32(const Plan P, const float *__restrict__ o, const float *__restrict_
 
 int launch_field_fp32(const Plan &P, int grid, const float *o, const float *v, const float *t,
                       const int32_t *ray_id, int64_t s_cap, const int64_t *s_count, float *f,
-                      float *g, float *rgb, float *ws, hipStream_t stream) {
-    if (g)
-        hipLaunchKernelGGL(k_field_fp32<true>, dim3(grid), dim3(kFThreads), 0, stream, P, o, v, t,
-                           ray_id, s_cap, s_count, f, g, rgb, ws);
-    else
-        hipLaunchKernelGGL(k_field_fp32<false>, dim3(grid), dim3(kFThreads), 0, stream, P, o, v, t,
-                           ray_id, s_cap, s_count, f, g, rgb, ws);
+                      float *g, float *rgb, float *ws, bool split, hipStream_t stream) {
+    auto kern = split ? (g ? k_field_fp32<true, true> : k_field_fp32<false, true>)
+                      : (g ? k_field_fp32<true, false> : k_field_fp32<false, false>);
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(kFThreads), 0, stream, P, o, v, t, ray_id, s_cap,
+                       s_count, f, g, rgb, ws);
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 

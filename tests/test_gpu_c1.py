@@ -138,23 +138,28 @@ def test_placement(c1):
     assert (np.abs(host(gp["dt"]) - op["dt"]) <= 2 * EPS32 * (tf / n + op["dt"])).all()
 
 
-def test_field_matches_oracle(c1):
+@pytest.mark.parametrize("prec", ["fp32", "bf16x6"])
+def test_field_matches_oracle(c1, prec):
+    """FP32 products, and FP32 operands as three-part BF16 products: the
+    same FP32 tolerances against the FP64 oracle."""
+    from paper_2311_17878_amd import _lib as L
+    precision = L.FP32 if prec == "fp32" else L.BF16X6
     cfg = c1["cfg"]
     ro, rv = c1["render"]
     p = c1["p"]
     t32 = p["t"].astype(np.float32)
     rid = p["ray_id"].astype(np.int32)
     F = make_field(cfg)
-    f, g, rgb = F.forward(dev(ro), dev(rv), dev(t32), dev(rid))
+    f, g, rgb = F.forward(dev(ro), dev(rv), dev(t32), dev(rid), precision=precision)
     torch.cuda.synchronize()
     of, og, orgb = OF.eval_samples(cfg, cfg.sdf_params(), cfg.color_params(), ro, rv, t32, rid)
     ef = np.abs(host(f) - of).max()
     eg = np.abs(host(g) - og).max()
     ec = np.abs(host(rgb) - orgb).max()
-    print("field max abs err: f %.3g  grad %.3g  rgb %.3g" % (ef, eg, ec))
+    print("%s field max abs err: f %.3g  grad %.3g  rgb %.3g" % (prec, ef, eg, ec))
     assert ef <= 2e-5 and eg <= 2e-4 and ec <= 2e-5
     # SDF-only mode gives the same f
-    f2, _, _ = F.forward(dev(ro), dev(rv), dev(t32), dev(rid), full=False)
+    f2, _, _ = F.forward(dev(ro), dev(rv), dev(t32), dev(rid), precision=precision, full=False)
     assert torch.equal(f2, f)
 
 
@@ -182,15 +187,18 @@ def test_composite_matches_oracle(c1):
     assert np.abs(host(out["normal"])[big] - ref["normal"][big]).max() <= 1e-4
 
 
-def test_render_end_to_end(c1):
+@pytest.mark.parametrize("prec", ["fp32", "bf16x6"])
+def test_render_end_to_end(c1, prec):
     """Whole path from the training rays: discrete outputs exact, depth within
-    1e-3 voxel on rays whose weights sum to more than 1%."""
-    from paper_2311_17878_amd import ops
+    1e-3 voxel on rays whose weights sum to more than 1% (FP32 products, and
+    FP32 operands as three-part BF16 products)."""
+    from paper_2311_17878_amd import ops, _lib as L
     from paper_2311_17878_amd.pipeline import TsdfRenderer
     cfg = c1["cfg"]
     s = cfg.sampling
     F = make_field(cfg)
-    R = TsdfRenderer(c1["grid"], F, s.rho_num, s.rho_den, s.n_min, s.n_max, cfg.neus_s)
+    R = TsdfRenderer(c1["grid"], F, s.rho_num, s.rho_den, s.n_min, s.n_max, cfg.neus_s,
+                     precision=L.FP32 if prec == "fp32" else L.BF16X6)
     o, v, d = c1["rays"]
     R.integrate(dev(o), dev(v), dev(d))
     R.finalize()

@@ -85,21 +85,25 @@ def test_bounds_and_placement_full_view(c2):
     assert (np.abs(host(p["t"])[:S] - op["t"]) <= 8 * EPS32 * tf).all()
 
 
-def test_field_on_sampled_samples(c2):
-    """The field over every sample of the view (FP32), checked at 2048 seeded
-    samples against the FP64 oracle."""
+@pytest.mark.parametrize("prec", ["fp32", "bf16x6"])
+def test_field_on_sampled_samples(c2, prec):
+    """The field over every sample of the view (FP32 products, and FP32
+    operands as three-part BF16 products), checked at 2048 seeded samples
+    against the FP64 oracle with the same tolerances."""
+    from paper_2311_17878_amd import _lib as L
     cfg, op = c2["cfg"], c2["op"]
     ro, rv = c2["render"]
     t32 = op["t"].astype(np.float32)
     rid = op["ray_id"].astype(np.int32)
-    f, g, rgb = c2["R"].field.forward(c2["ro_d"], c2["rv_d"], dev(t32), dev(rid))
+    f, g, rgb = c2["R"].field.forward(c2["ro_d"], c2["rv_d"], dev(t32), dev(rid),
+                                      precision=L.FP32 if prec == "fp32" else L.BF16X6)
     torch.cuda.synchronize()
     pick = np.sort(np.random.default_rng(0).choice(t32.size, 2048, replace=False))
     of, og, orgb = OF.eval_samples(cfg, cfg.sdf_params(), cfg.color_params(), ro, rv, t32[pick], rid[pick])
     ef = np.abs(host(f)[pick] - of)
     eg = np.abs(host(g)[pick] - og)
     ec = np.abs(host(rgb)[pick] - orgb)
-    print("C2 field abs err max: f %.3g grad %.3g rgb %.3g" % (ef.max(), eg.max(), ec.max()))
+    print("C2 %s field abs err max: f %.3g grad %.3g rgb %.3g" % (prec, ef.max(), eg.max(), ec.max()))
     # FP32 products of depth 9 with K <= 272; f in metres = scale (2) x the
     # network's normalised output, so 1e-5 normalised is 2e-5 m
     scale = float(cfg.in_scale)
@@ -131,14 +135,25 @@ def _sampled_rays(c2):
     return _RAYS["rays"], _RAYS["ref"]
 
 
-def test_render_on_sampled_rays(c2):
+@pytest.mark.parametrize("prec", ["fp32", "bf16x6"])
+def test_render_on_sampled_rays(c2, prec):
+    from paper_2311_17878_amd import _lib as L
+    R = c2["R"]
+    R.precision = L.FP32 if prec == "fp32" else L.BF16X6
+    try:
+        _render_on_sampled_rays(c2, prec)
+    finally:
+        R.precision = L.FP32
+
+
+def _render_on_sampled_rays(c2, prec):
     out = c2["R"].render(c2["ro_d"], c2["rv_d"])
     torch.cuda.synchronize()
     rays, ref = _sampled_rays(c2)
     h = c2["g"].h
     for k, tol in (("rgb", 1e-4), ("acc", 1e-4)):
         e = np.abs(host(out[k])[rays] - ref[k]).max()
-        print(k, e)
+        print(prec, k, e)
         assert e <= tol, k
     big = ref["acc"] > 1e-2
     if big.any():

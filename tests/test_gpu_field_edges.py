@@ -1,4 +1,5 @@
-"""GPU parity of the fused field kernels (FP32 and BF16, through the C ABI)
+"""GPU parity of the fused field kernels (FP32, BF16 and FP32 operands as
+three-part BF16 products, through the C ABI)
 at ragged sample counts: one sample, the tile size and its neighbours, sizes
 that leave a ragged last tile.  A sample's outputs do not depend on the other
 samples of its launch, so every small launch must equal, bit for bit, the same
@@ -48,12 +49,19 @@ def samples(cfg, n, seed=7):
     return o, v, t, rid
 
 
+PRECISIONS = ["fp32", "bf16", "bf16x6"]
+
+
+def _precision(L, prec):
+    return {"fp32": L.FP32, "bf16": L.BF16, "bf16x6": L.BF16X6}[prec]
+
+
 @pytest.mark.parametrize("name", ["c1", "c2"])
-@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+@pytest.mark.parametrize("prec", PRECISIONS)
 def test_ragged_sizes_equal_one_large_launch(name, prec):
     from paper_2311_17878_amd import _lib as L
     cfg = get_config(name)
-    precision = L.FP32 if prec == "fp32" else L.BF16
+    precision = _precision(L, prec)
     o, v, t, rid = samples(cfg, N_BIG)
     F = make_field(cfg)
     od, vd = dev(o), dev(v)
@@ -65,23 +73,23 @@ def test_ragged_sizes_equal_one_large_launch(name, prec):
             for a, b, what in zip(out, big, ("f", "grad f", "rgb")):
                 assert a.shape[0] == n
                 assert torch.equal(a, b[sl]), "%s: n=%d shift=%d differs in %s" % (prec, n, k, what)
-    if prec == "fp32":
+    if prec != "bf16":
         of, og, orgb = OF.eval_samples(cfg, cfg.sdf_params(), cfg.color_params(), o, v, t, rid)
         ef = np.abs(host(big[0]) - of).max()
         eg = np.abs(host(big[1]) - og).max()
         ec = np.abs(host(big[2]) - orgb).max()
-        print("%s FP32 at %d samples: max abs err f %.3g grad %.3g rgb %.3g" % (name, N_BIG, ef, eg, ec))
+        print("%s %s at %d samples: max abs err f %.3g grad %.3g rgb %.3g" % (name, prec, N_BIG, ef, eg, ec))
         assert ef <= 1e-4 and eg <= 2e-4 and ec <= 2e-5
 
 
-@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+@pytest.mark.parametrize("prec", PRECISIONS)
 def test_device_sample_count(prec):
     """s_count_dev below, at and above s_cap: min(count, cap) samples are
     evaluated, equal to a plain launch of that many; the rest of the outputs
     keep what they held."""
     from paper_2311_17878_amd import _lib as L, ops
     cfg = get_config("c2")
-    precision = L.FP32 if prec == "fp32" else L.BF16
+    precision = _precision(L, prec)
     cap = 300
     o, v, t, rid = samples(cfg, cap, seed=11)
     F = make_field(cfg)
@@ -104,3 +112,22 @@ def test_device_sample_count(prec):
         for a, b in zip((f, g, rgb), ref):
             assert torch.equal(a[:m], b[:m]), (prec, count)
             assert bool(torch.isnan(a[m:]).all()), (prec, count)
+
+
+def test_split_precision_is_forward_only():
+    """The three-part BF16 products are a forward mode: sdf_mlp_bwd refuses
+    them (TSDFS_EUNSUPPORTED), as it refuses any unknown precision value, and
+    so does sdf_mlp_fwd for a value past the last mode."""
+    from paper_2311_17878_amd import _lib as L
+    cfg = get_config("c1")
+    o, v, t, rid = samples(cfg, 64, seed=3)
+    F = make_field(cfg)
+    args = (dev(o), dev(v), dev(t), dev(rid))
+    with pytest.raises(L.TsdfsError) as e:
+        F.forward(*args, precision=L.BF16X6 + 1)
+    assert e.value.code == L.TSDFS_EUNSUPPORTED
+    f, g, rgb = F.forward(*args, precision=L.BF16X6)
+    with pytest.raises(L.TsdfsError) as e:
+        F.backward(*args, d_f=torch.ones_like(f), d_grad=torch.zeros_like(g),
+                   d_rgb=torch.zeros_like(rgb), precision=L.BF16X6)
+    assert e.value.code == L.TSDFS_EUNSUPPORTED
