@@ -40,8 +40,10 @@ FIELD_SOURCES = {"k_field_fp32": ["field_fp32.hip", "field_common.hpp", "common.
                  "k_field_bf16": ["field_bf16.hip", "field_bf16_layout.hpp", "field_common.hpp",
                                   "common.hpp", "field.hip"]}
 TRAFFIC = {
-    "k_field_fp32": {"sha256_16": "f3645b604ee31a4d", "fetch_kib": 3.4028e+07, "write_kib": 5.7852e+07},
-    "k_field_bf16": {"sha256_16": "25b5b12f71966893", "fetch_kib": 1.3270e+07, "write_kib": 2.1042e+07},
+    "k_field_fp32": {"sha256_16": "87ddab944ac78476", "fetch_kib": 3.6421e+07, "write_kib": 5.7854e+07},
+    "k_field_fp32_split": {"sha256_16": "87ddab944ac78476", "fetch_kib": 3.9673e+07,
+                           "write_kib": 5.8033e+07},
+    "k_field_bf16": {"sha256_16": "143471f6598e3903", "fetch_kib": 1.3242e+07, "write_kib": 2.1042e+07},
 }
 COPY_SCALE = {"fetch": 2.0, "write": 1.0}
 

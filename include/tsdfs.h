@@ -330,11 +330,12 @@ typedef struct tsdfs_field tsdfs_field;
 /* Precision of the field's matrix products (sdf_mlp_fwd, sdf_mlp_bwd).
  * TSDFS_FP32: FP32 operands on the FP32 matrix cores.  TSDFS_BF16: operands
  * rounded to BF16 (nearest even), FP32 accumulation.  TSDFS_BF16X6 (forward
- * only): FP32 operands, each the exact sum of three BF16 parts, multiplied
- * on the BF16 matrix cores as the six part products that can reach 2^-24 of
- * the whole, with FP32 accumulation (the three dropped ones stay below
- * 2^-26 of it): FP32 accuracy at BF16 matrix-core rates.  Everything outside
- * the products is FP32 in all three. */
+ * only): FP32 operands, each the exact sum of three BF16 parts
+ * (|mid| <= 2^-8 |x|, |lo| <= 2^-16 |x|), multiplied on the BF16 matrix
+ * cores as the six part products down to 2^-16 of |w| |x|, with FP32
+ * accumulation; the three dropped ones are together below 1.01 * 2^-23 of
+ * |w| |x|, about one FP32 rounding: FP32-level accuracy at BF16
+ * matrix-core rates.  Everything outside the products is FP32 in all three. */
 enum { TSDFS_FP32 = 0, TSDFS_BF16 = 1, TSDFS_BF16X6 = 2 };
 
 int tsdfs_field_create(const tsdfs_field_desc *desc, const float *sdf_params_host,

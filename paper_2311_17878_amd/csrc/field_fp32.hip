@@ -174,10 +174,11 @@ __device__ __forceinline__ bf16x8 as_bf16x8(const uint32_t (&w)[4]) {
 
 // The product of gemm_f on v_mfma_f32_32x32x16_bf16 with both operands in
 // three BF16 parts (weights pre-split in W3, activations split from the FP32
-// act rows per K-step of 16): per step the six part products that can reach
-// 2^-24 of the whole, smallest first (lo.hi, hi.lo, mid.mid, mid.hi,
-// hi.mid, hi.hi); the dropped mid.lo, lo.mid and lo.lo stay below 2^-26 of
-// it.  Every part product is exact in the FP32 accumulator.  Software
+// act rows per K-step of 16; |mid| <= 2^-8 |x| and |lo| <= 2^-16 |x|): per
+// step the six part products down to 2^-16 of |w| |x|, smallest first
+// (lo.hi, hi.lo, mid.mid, mid.hi, hi.mid, hi.hi); the dropped mid.lo, lo.mid
+// and lo.lo are together below 1.01 * 2^-23 of |w| |x|, about one FP32
+// rounding.  Every part product is exact in the FP32 accumulator.  Software
 // pipelined: the split of step k + 1 (VALU, one pair of values at a time) is
 // interleaved in program order with the products of step k (MFMA), its B
 // values loaded just before; the A parts of step k + 2 load after the
