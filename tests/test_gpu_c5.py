@@ -134,7 +134,7 @@ def c5_render(c5):
     ref = _oracle_render(c5, rays)
     R = c5["R"]
     outs = {}
-    for name, prec in (("fp32", L.FP32), ("bf16", L.BF16)):
+    for name, prec in (("fp32", L.FP32), ("bf16", L.BF16), ("bf16x6", L.BF16X6)):
         R.precision = prec
         try:
             out = R.render(dev(c5["ro"]), dev(c5["rv"]))
@@ -160,6 +160,15 @@ def test_panorama_render_fp32(c5, c5_render):
           "p99 %.3g h | rgb max %.3g | acc max %.3g" %
           (big.sum(), ed.max(), np.percentile(ed, 99), ec.max(), ea.max()))
     assert big.sum() > 64
+    assert ed.max() <= 1e-3 and ec.max() <= 1e-4 and ea.max() <= 1e-4
+
+
+def test_panorama_render_split(c5, c5_render):
+    """FP32 operands as three-part BF16 products: the FP32 bounds."""
+    rays, ref, outs = c5_render
+    big, ed, ec, ea = _errors(c5, rays, ref, outs["bf16x6"])
+    print("C5 split-product vs oracle on 256 rays: depth err max %.3g h, p99 %.3g h | rgb max %.3g "
+          "| acc max %.3g" % (ed.max(), np.percentile(ed, 99), ec.max(), ea.max()))
     assert ed.max() <= 1e-3 and ec.max() <= 1e-4 and ea.max() <= 1e-4
 
 
