@@ -658,7 +658,8 @@ def main():
         teik = cfg.eikonal_points(8192, seed=0)
         tro, trv, ttarget, teik = dev(tro), dev(trv), dev(ttarget), dev(teik)
         n_t = max(1, min(args.steps, 5))
-        for tname, tprec in (("train_step", _lib.FP32), ("train_step_bf16", _lib.BF16)):
+        for tname, tprec in (("train_step", _lib.FP32), ("train_step_bf16", _lib.BF16),
+                             ("train_step_bf16x6", _lib.BF16X6)):
             out_t = train_step(R, tro, trv, ttarget, teik, precision=tprec)   # warm-up
             torch.cuda.synchronize()
             start.record()
@@ -670,14 +671,20 @@ def main():
             S_t = int(out_t[4])
             t_flop = S_t * fl_sample + (S_t + 8192) * train_flops_per_row(cfg.sdf, cfg.color)
             t_peak = PEAK_TFLOPS["f32" if tprec == _lib.FP32 else "bf16"]
+            # the split form runs six BF16 products per FP32 one
+            t_work = 6 if tprec == _lib.BF16X6 else 1
             result[tname] = {
                 "rays": 8192, "eikonal_points": 8192, "samples": S_t, "ms_per_step": tms,
                 "rays_per_s": 8192 / (tms * 1e-3),
                 "flop_per_step": t_flop, "tflop_per_s": t_flop / (tms * 1e-3) / 1e12,
-                "mfma_frac": t_flop / (tms * 1e-3) / 1e12 / t_peak,
+                "mfma_frac": t_work * t_flop / (tms * 1e-3) / 1e12 / t_peak,
                 "loss_rgb": float(out_t[0].item()), "loss_eik": float(out_t[1].item()),
-                "precision": "f32 (forward and backward)" if tprec == _lib.FP32 else
-                             "bf16 product inputs, f32 accumulation (forward and backward)",
+                "precision": {_lib.FP32: "f32 (forward and backward)",
+                              _lib.BF16: "bf16 product inputs, f32 accumulation (forward and "
+                                         "backward)",
+                              _lib.BF16X6: "f32 operands as three-part bf16 products (six per "
+                                           "f32 product, f32 accumulation; forward and "
+                                           "backward)"}[tprec],
             }
             log(f"{tname}: {tms:.2f} ms")
         # a multi-step training loop: train_step, Adam over the field's
@@ -689,7 +696,8 @@ def main():
             bo, bv, bt = cfg.training_batch(8192, seed=100 + k)
             bl.append((dev(bo), dev(bv), dev(bt), dev(cfg.eikonal_points(8192, seed=100 + k))))
         n_loop = max(2, min(args.steps, 10))
-        for lname, lprec in (("train_loop", _lib.FP32), ("train_loop_bf16", _lib.BF16)):
+        for lname, lprec in (("train_loop", _lib.FP32), ("train_loop_bf16", _lib.BF16),
+                             ("train_loop_bf16x6", _lib.BF16X6)):
             fl = ops.Field(cfg.sdf.width, cfg.sdf.n_hidden, cfg.sdf.pe_freqs, cfg.sdf.skip_at,
                            cfg.sdf.n_feat, cfg.color.n_hidden, cfg.sdf.beta, cfg.in_center,
                            cfg.in_scale, cfg.sdf_params(), cfg.color_params())

@@ -329,8 +329,8 @@ typedef struct tsdfs_field tsdfs_field;
 
 /* Precision of the field's matrix products (sdf_mlp_fwd, sdf_mlp_bwd).
  * TSDFS_FP32: FP32 operands on the FP32 matrix cores.  TSDFS_BF16: operands
- * rounded to BF16 (nearest even), FP32 accumulation.  TSDFS_BF16X6 (forward
- * only): FP32 operands, each the exact sum of three BF16 parts
+ * rounded to BF16 (nearest even), FP32 accumulation.  TSDFS_BF16X6: FP32
+ * operands, each the exact sum of three BF16 parts
  * (|mid| <= 2^-8 |x|, |lo| <= 2^-16 |x|), multiplied on the BF16 matrix
  * cores as the six part products down to 2^-16 of |w| |x|, with FP32
  * accumulation; the three dropped ones are together below 1.01 * 2^-23 of
@@ -415,10 +415,11 @@ int composite(const int32_t *offsets, int64_t n_rays, const float *v, const floa
  * second-order terms through grad f (colour input, opacity, eikonal).
  * Activations are recomputed inside the call (none are kept from
  * sdf_mlp_fwd).  d_f, d_grad_f may be NULL (zero).  eik_loss (optional,
- * device float) receives the eikonal term.  precision: TSDFS_FP32, or
+ * device float) receives the eikonal term.  precision: TSDFS_FP32,
  * TSDFS_BF16 (every matrix product takes BF16-rounded inputs with FP32
- * accumulation; elementwise work, bias sums and outputs stay FP32); other
- * values (TSDFS_BF16X6 included): TSDFS_EUNSUPPORTED.  Every
+ * accumulation; elementwise work, bias sums and outputs stay FP32) or
+ * TSDFS_BF16X6 (FP32 operands as three-part BF16 products, everything
+ * stored in FP32); other values: TSDFS_EUNSUPPORTED.  Every
  * product runs in the library's own MFMA kernels; the weight gradients and
  * the bias and loss sums reduce over the rows in a fixed order, so repeated
  * calls give identical bits.  No allocation.

@@ -65,8 +65,9 @@ def train_step(renderer, o, v, target, eik_x, eik_lambda=0.1, precision=FP32):
     """One TSDF-bounded training step on a batch of rays (C ABI only):
     Alg. 1 bounds -> placement -> field -> compositing -> photometric loss,
     then the compositing adjoint and the network backward with the eikonal
-    term on eik_x.  precision selects FP32 or BF16-input products for the
-    field forward and the network backward.  Returns (loss_rgb, loss_eik,
+    term on eik_x.  precision selects FP32 products, BF16-input products or
+    FP32 operands as three-part BF16 products for the field forward and the
+    network backward.  Returns (loss_rgb, loss_eik,
     d_sdf, d_col, n_samples)."""
     R = renderer
     b = ops.ray_bounds(R.grid, R.flags, o, v, R.t_far)

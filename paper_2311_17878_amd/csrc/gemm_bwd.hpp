@@ -1,7 +1,7 @@
 // Matrix products of the training backward on the MFMA units (FP32:
-// v_mfma_f32_32x32x2_f32; BF16 inputs: v_mfma_f32_32x32x16_bf16, both with
-// FP32 accumulation), with the elementwise step that follows a product run
-// in its epilogue.
+// v_mfma_f32_32x32x2_f32; BF16 inputs, and FP32 operands as three BF16
+// parts: v_mfma_f32_32x32x16_bf16; all with FP32 accumulation), with the
+// elementwise step that follows a product run in its epilogue.
 //
 // Two shapes occur.  Row products C[R, N] = A[R, K] op(W) run over the
 // ~10^5 rows (samples and eikonal points) of a step against one weight
@@ -16,8 +16,13 @@
 // 16-byte LDS load.  In FP32 the 8 k of a group are taken as k = 4 h + s in
 // step s by the lanes of half h = lane / 32 (A and B alike, so each product
 // sums over all 8).  BF16 operands are rounded (nearest even) when they are
-// written to LDS, so no converted copy of an input exists in HBM.  Global
-// loads of the next K step are issued before the MFMAs of the current one.
+// written to LDS, so no converted copy of an input exists in HBM.  In the
+// split form (PM = kSplit) every FP32 element is written to LDS as its three
+// BF16 parts hi + mid + lo (exact; three planes), and each product is the six
+// part products down to 2^-16 of |a| |b| (lo.hi, hi.lo, mid.mid, mid.hi,
+// hi.mid, hi.hi; the dropped three are together below 1.01 * 2^-23 of
+// |a| |b|).  Global loads of the next K step are issued before the MFMAs of
+// the current one.
 #pragma once
 
 #include "field_common.hpp"
@@ -28,15 +33,44 @@ namespace bwd {
 constexpr int kBM = 128;
 constexpr int kThreads = 256;
 
-template <bool BF> struct Prec;
-template <> struct Prec<false> {
-    static constexpr int BK = 32, LS = 36, V = 4;   // k per tile, LDS row stride, k per store
+// product precisions: FP32, BF16 inputs, FP32 operands as three BF16 parts
+enum { kF32 = 0, kBf16 = 1, kSplit = 2 };
+
+template <int PM> struct Prec;
+template <> struct Prec<kF32> {
+    // k per tile, LDS row stride, k per store, LDS planes
+    static constexpr int BK = 32, LS = 36, V = 4, PL = 1;
     typedef float T;
 };
-template <> struct Prec<true> {
-    static constexpr int BK = 64, LS = 72, V = 8;
+template <> struct Prec<kBf16> {
+    static constexpr int BK = 64, LS = 72, V = 8, PL = 1;
     typedef __bf16 T;
 };
+template <> struct Prec<kSplit> {
+    static constexpr int BK = 32, LS = 40, V = 4, PL = 3;
+    typedef __bf16 T;
+};
+
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef float floatx2 __attribute__((ext_vector_type(2)));
+
+// Two FP32 values as three BF16 parts each (one 32-bit word of each part):
+// hi the nearest-even BF16 of x, mid that of x - hi, lo that of
+// x - hi - mid; both differences are exact (each operand is within a factor
+// of two of the value it is subtracted from) and leave at most eight
+// significant bits for lo, so x = hi + mid + lo.
+__device__ __forceinline__ void split_pair(float x0, float x1, uint32_t &h, uint32_t &m,
+                                           uint32_t &l) {
+    const floatx2 v = {x0, x1};
+    const bf16x2 a = __builtin_convertvector(v, bf16x2);
+    const floatx2 r = v - __builtin_convertvector(a, floatx2);
+    const bf16x2 b = __builtin_convertvector(r, bf16x2);
+    const floatx2 r2 = r - __builtin_convertvector(b, floatx2);
+    const bf16x2 c = __builtin_convertvector(r2, bf16x2);
+    h = __builtin_bit_cast(uint32_t, a);
+    m = __builtin_bit_cast(uint32_t, b);
+    l = __builtin_bit_cast(uint32_t, c);
+}
 
 // An operand as a function of (i, k): i indexes output rows (A) or output
 // columns (B), k the reduction.  kcont: element at p[i ld + k], else
@@ -59,11 +93,11 @@ enum { LD_KVEC = 0, LD_ICONT = 2 };
 // store (the entries of an item that are valid form a prefix in k).
 // S = float: FP32 elements in memory; S = __bf16 (BF16 products only):
 // BF16 elements, kept as raw 16-bit words until the store.
-template <bool BF, int NI, int MODE, typename S = float>
+template <int PM, int NI, int MODE, typename S = float>
 struct Loader {
-    typedef Prec<BF> P;
+    typedef Prec<PM> P;
     static constexpr bool SB = sizeof(S) == 2;
-    static_assert(!SB || BF, "BF16 operands feed BF16 products only");
+    static_assert(!SB || PM == kBf16, "BF16 operands feed BF16 products only");
     static constexpr int ITEMS = NI * (P::BK / P::V) / kThreads;
     float r[SB ? 1 : ITEMS][P::V];
     uint32_t w[SB ? ITEMS : 1][P::V / 2];   // BF16: element pairs (low half first)
@@ -170,7 +204,15 @@ struct Loader {
                 float x[P::V];
 #pragma unroll
                 for (int u = 0; u < P::V; ++u) x[u] = u < nv[q] ? r[q][u] : 0.0f;
-                if constexpr (BF) {
+                if constexpr (PM == kSplit) {   // planes hi, mid, lo of NI rows each
+                    uint32_t h[2], m[2], l[2];
+#pragma unroll
+                    for (int u = 0; u < 2; ++u) split_pair(x[2 * u], x[2 * u + 1], h[u], m[u], l[u]);
+                    typename P::T *d = lds + row * P::LS + kv;
+                    *(uint2 *)d = make_uint2(h[0], h[1]);
+                    *(uint2 *)(d + NI * P::LS) = make_uint2(m[0], m[1]);
+                    *(uint2 *)(d + 2 * NI * P::LS) = make_uint2(l[0], l[1]);
+                } else if constexpr (PM == kBf16) {
                     bf16x8 h;
 #pragma unroll
                     for (int u = 0; u < 8; ++u) h[u] = (__bf16)x[u];   // RNE
@@ -190,14 +232,42 @@ struct Acc {
     floatx16 a[RB][CB];
 };
 
-template <bool BF, int RB, int CB, int WC>
-__device__ __forceinline__ void mma_tile(const typename Prec<BF>::T *As,
-                                         const typename Prec<BF>::T *Bs, Acc<RB, CB> &acc,
+// NA, NB: rows of the A and B tiles in LDS (the plane stride of the split
+// form)
+template <int PM, int RB, int CB, int WC, int NA = kBM, int NB = WC * CB * 32>
+__device__ __forceinline__ void mma_tile(const typename Prec<PM>::T *As,
+                                         const typename Prec<PM>::T *Bs, Acc<RB, CB> &acc,
                                          int wave, int lane) {
-    typedef Prec<BF> P;
+    typedef Prec<PM> P;
     const int wr = wave / WC, wc = wave % WC;
     const int l32 = lane & 31, h = lane >> 5;
-    if constexpr (!BF) {
+    if constexpr (PM == kSplit) {
+#pragma unroll
+        for (int s = 0; s < P::BK / 16; ++s) {
+            bf16x8 a[3][RB], b[3][CB];
+#pragma unroll
+            for (int p = 0; p < 3; ++p) {
+#pragma unroll
+                for (int rb = 0; rb < RB; ++rb)
+                    a[p][rb] = *(const bf16x8 *)(As + p * NA * P::LS +
+                                                 ((wr * RB + rb) * 32 + l32) * P::LS + 16 * s + 8 * h);
+#pragma unroll
+                for (int cb = 0; cb < CB; ++cb)
+                    b[p][cb] = *(const bf16x8 *)(Bs + p * NB * P::LS +
+                                                 ((wc * CB + cb) * 32 + l32) * P::LS + 16 * s + 8 * h);
+            }
+            // parts (of A, of B) per product, smallest first; 0 hi, 1 mid, 2 lo
+            constexpr int pa[6] = {2, 0, 1, 1, 0, 0}, pb[6] = {0, 2, 1, 0, 1, 0};
+#pragma unroll
+            for (int t = 0; t < 6; ++t)
+#pragma unroll
+                for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+                    for (int cb = 0; cb < CB; ++cb)
+                        acc.a[rb][cb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+                            a[pa[t]][rb], b[pb[t]][cb], acc.a[rb][cb], 0, 0, 0);
+        }
+    } else if constexpr (PM == kF32) {
 #pragma unroll
         for (int g = 0; g < P::BK / 8; ++g) {
             float4 a[RB], b[CB];
@@ -240,21 +310,21 @@ __device__ __forceinline__ void mma_tile(const typename Prec<BF>::T *As,
 // sum over k in [k_begin, k_end) of A(i0 + ., k) B(j0 + ., k) into acc.
 // With a_sum (A in LD_ICONT mode), *a_sum also receives this thread's share
 // of sum_k A(i0 + tid % 128, k) (FP32; tid and tid + 128 share a row).
-template <bool BF, int RB, int CB, int WC, int AMODE, int BMODE, typename SA = float,
+template <int PM, int RB, int CB, int WC, int AMODE, int BMODE, typename SA = float,
           typename SB = float>
 __device__ __forceinline__ void tile_product(const Opnd &A, const Opnd &B, int i0, int j0,
                                              int k_begin, int k_end, Acc<RB, CB> &acc,
-                                             typename Prec<BF>::T *As, typename Prec<BF>::T *Bs,
+                                             typename Prec<PM>::T *As, typename Prec<PM>::T *Bs,
                                              float *a_sum = nullptr) {
-    typedef Prec<BF> P;
+    typedef Prec<PM> P;
     constexpr int BN = WC * CB * 32;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
 #pragma unroll
     for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
         for (int cb = 0; cb < CB; ++cb) acc.a[rb][cb] = (floatx16)(0.0f);
-    Loader<BF, kBM, AMODE, SA> la;
-    Loader<BF, BN, BMODE, SB> lb;
+    Loader<PM, kBM, AMODE, SA> la;
+    Loader<PM, BN, BMODE, SB> lb;
     if (k_begin < k_end) {
         la.load(A, i0, k_begin, tid);
         lb.load(B, j0, k_begin, tid);
@@ -269,7 +339,7 @@ __device__ __forceinline__ void tile_product(const Opnd &A, const Opnd &B, int i
             la.load(A, i0, k0 + P::BK, tid);
             lb.load(B, j0, k0 + P::BK, tid);
         }
-        mma_tile<BF, RB, CB, WC>(As, Bs, acc, wave, lane);
+        mma_tile<PM, RB, CB, WC>(As, Bs, acc, wave, lane);
     }
 }
 

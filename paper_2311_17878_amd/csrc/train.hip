@@ -242,22 +242,24 @@ __device__ __forceinline__ void epilogue(const Epi &e, const bwd::Acc<RB, CB> &a
 // by multiples of 8, so they share an XCD and its L2.
 constexpr int kXcd = 8;
 
-// SA: the A operand's element type in memory; the B operand (staged
-// weights) is BF16 for BF16 products, else FP32
-template <bool BF, int RB, int CB, int WC, typename SA>
+// PM: bwd::kF32, kBf16 or kSplit (FP32 operands as three BF16 parts).  SA:
+// the A operand's element type in memory; the B operand (staged weights) is
+// BF16 for BF16 products, else FP32
+template <int PM, int RB, int CB, int WC, typename SA>
 __global__ void __launch_bounds__(bwd::kThreads) k_row(Opnd A, Opnd B, int R, int N, int j_base,
                                                        int n_rt, int n_nt, Epi e) {
-    typedef bwd::Prec<BF> P;
+    typedef bwd::Prec<PM> P;
+    constexpr bool BF = PM == bwd::kBf16;
     constexpr int BN = WC * CB * 32;
-    __shared__ __attribute__((aligned(16))) typename P::T As[bwd::kBM * P::LS];
-    __shared__ __attribute__((aligned(16))) typename P::T Bs[BN * P::LS];
+    __shared__ __attribute__((aligned(16))) typename P::T As[P::PL * bwd::kBM * P::LS];
+    __shared__ __attribute__((aligned(16))) typename P::T Bs[P::PL * BN * P::LS];
     const int id = blockIdx.x, q = id / kXcd;
     const int nt = q % n_nt, rt = (q / n_nt) * kXcd + id % kXcd;
     if (rt >= n_rt) return;   // uniform over the workgroup
     const int i0 = rt * bwd::kBM, j0 = j_base + nt * BN;
     bwd::Acc<RB, CB> acc;
     typedef typename std::conditional<BF, __bf16, float>::type SW;
-    bwd::tile_product<BF, RB, CB, WC, bwd::LD_KVEC, bwd::LD_KVEC, SA, SW>(A, B, i0, j0, 0, A.n_k,
+    bwd::tile_product<PM, RB, CB, WC, bwd::LD_KVEC, bwd::LD_KVEC, SA, SW>(A, B, i0, j0, 0, A.n_k,
                                                                           acc, As, Bs);
     epilogue<BF, RB, CB, WC>(e, acc, i0, j0, R, N);
 }
@@ -265,14 +267,14 @@ __global__ void __launch_bounds__(bwd::kThreads) k_row(Opnd A, Opnd B, int R, in
 // Weight gradients: partial products per chunk of rows; the workgroups of
 // the first column tile also form the chunk's column sums of A (the bias
 // gradients) when bpart is set.
-template <bool BF, typename SA, typename SB>
+template <int PM, typename SA, typename SB>
 __global__ void __launch_bounds__(bwd::kThreads, 2) k_wgrad(Opnd A, Opnd B, int M, int N, int R,
                                                          int kc, int n_mt, int n_nt, int n_ch,
                                                          float *__restrict__ part,
                                                          float *__restrict__ bpart) {
-    typedef bwd::Prec<BF> P;
-    __shared__ __attribute__((aligned(16))) typename P::T As[bwd::kBM * P::LS];
-    __shared__ __attribute__((aligned(16))) typename P::T Bs[bwd::kBM * P::LS];
+    typedef bwd::Prec<PM> P;
+    __shared__ __attribute__((aligned(16))) typename P::T As[P::PL * bwd::kBM * P::LS];
+    __shared__ __attribute__((aligned(16))) typename P::T Bs[P::PL * bwd::kBM * P::LS];
     __shared__ float red[bwd::kThreads];
     const int id = blockIdx.x, q = id / kXcd;
     const int tile = q % (n_mt * n_nt), ch = (q / (n_mt * n_nt)) * kXcd + id % kXcd;
@@ -283,7 +285,7 @@ __global__ void __launch_bounds__(bwd::kThreads, 2) k_wgrad(Opnd A, Opnd B, int 
     const bool sums = bpart != nullptr && nt == 0;
     float a_sum = 0.0f;
     bwd::Acc<2, 2> acc;
-    bwd::tile_product<BF, 2, 2, 2, bwd::LD_ICONT, bwd::LD_ICONT, SA, SB>(
+    bwd::tile_product<PM, 2, 2, 2, bwd::LD_ICONT, bwd::LD_ICONT, SA, SB>(
         A, B, i0, j0, k_begin, k_end, acc, As, Bs, sums ? &a_sum : nullptr);
     float *out = part + (size_t)ch * M * N;
     bwd::for_each<2, 2, 2>(acc, i0, j0, M, N,
@@ -327,10 +329,11 @@ static int chunk_rows(int R) {
 
 struct Ctx {
     hipStream_t st;
-    bool bf16;
+    bool bf16;          // BF16 products (operands may be stored in BF16)
     float *part;        // weight-gradient partials
     size_t part_cap;    // floats in part
     float *bpart;       // bias-gradient partials [kMaxChunks][<= wide]
+    bool split;         // FP32 operands as three BF16 parts (FP32 storage)
 };
 
 // 16-byte loads of 4 FP32 or 8 BF16 elements stay inside a row
@@ -340,29 +343,29 @@ static bool vec_ok(const void *p, int ld, int k, bool bf) {
 }
 
 // Columns [j_base, j_base + ncols) of a row product in tiles of 32 NB.
-template <bool BF, typename SA>
+template <int PM, typename SA>
 static void launch_row(const Ctx &c, int nb, const Opnd &A, const Opnd &B, int R, int N,
                        int j_base, int ncols, const Epi &e) {
     const int n_rt = (R + bwd::kBM - 1) / bwd::kBM;
     const int n_nt = (ncols + 32 * nb - 1) / (32 * nb);
     const unsigned grid = (unsigned)((n_rt + kXcd - 1) / kXcd * kXcd * n_nt);
     if (nb == 4)
-        hipLaunchKernelGGL((k_row<BF, 2, 2, 2, SA>), dim3(grid), dim3(bwd::kThreads), 0, c.st, A, B, R,
+        hipLaunchKernelGGL((k_row<PM, 2, 2, 2, SA>), dim3(grid), dim3(bwd::kThreads), 0, c.st, A, B, R,
                            N, j_base, n_rt, n_nt, e);
     else if (nb == 2)
-        hipLaunchKernelGGL((k_row<BF, 1, 2, 1, SA>), dim3(grid), dim3(bwd::kThreads), 0, c.st, A, B, R,
+        hipLaunchKernelGGL((k_row<PM, 1, 2, 1, SA>), dim3(grid), dim3(bwd::kThreads), 0, c.st, A, B, R,
                            N, j_base, n_rt, n_nt, e);
     else
-        hipLaunchKernelGGL((k_row<BF, 1, 1, 1, SA>), dim3(grid), dim3(bwd::kThreads), 0, c.st, A, B, R,
+        hipLaunchKernelGGL((k_row<PM, 1, 1, 1, SA>), dim3(grid), dim3(bwd::kThreads), 0, c.st, A, B, R,
                            N, j_base, n_rt, n_nt, e);
 }
 
-template <bool BF, typename SA>
+template <int PM, typename SA>
 static void row_tiles(const Ctx &c, const Opnd &A, const Opnd &B, int R, int N, const Epi &e) {
     const int nfull = N / 128 * 128, rem = N - nfull;
-    if (nfull > 0) launch_row<BF, SA>(c, 4, A, B, R, N, 0, nfull, e);
+    if (nfull > 0) launch_row<PM, SA>(c, 4, A, B, R, N, 0, nfull, e);
     if (rem > 0)
-        launch_row<BF, SA>(c, rem <= 32 ? 1 : rem <= 64 ? 2 : 4, A, B, R, N, nfull, rem, e);
+        launch_row<PM, SA>(c, rem <= 32 ? 1 : rem <= 64 ? 2 : 4, A, B, R, N, nfull, rem, e);
 }
 
 // C[r][n] (r < R, n < N) = sum_{k < K} A[r lda + k] W[n ldw + k] through the
@@ -382,12 +385,14 @@ static int gemm_row(const Ctx &c, int R, int N, int K, const void *A, bool a_bf,
     }
     const Opnd a{A, lda, R, K};
     const Opnd b{W, ldw, N, K};
-    if (!c.bf16)
-        row_tiles<false, float>(c, a, b, R, N, e);
+    if (c.split)
+        row_tiles<bwd::kSplit, float>(c, a, b, R, N, e);
+    else if (!c.bf16)
+        row_tiles<bwd::kF32, float>(c, a, b, R, N, e);
     else if (a_bf)
-        row_tiles<true, __bf16>(c, a, b, R, N, e);
+        row_tiles<bwd::kBf16, __bf16>(c, a, b, R, N, e);
     else
-        row_tiles<true, float>(c, a, b, R, N, e);
+        row_tiles<bwd::kBf16, float>(c, a, b, R, N, e);
     TSDFS_LAUNCH_CHECK();
     return TSDFS_OK;
 }
@@ -413,19 +418,21 @@ static int gemm_wgrad(const Ctx &c, int R, int M, int N, const void *A, bool a_b
     const Opnd b{B, ldb, N, R};
     const unsigned grid = (unsigned)((n_ch + kXcd - 1) / kXcd * kXcd * n_mt * n_nt);
     float *bp = bias ? c.bpart : nullptr;
-#define TSDFS_WGRAD(BF, SA, SB)                                                            \
-    hipLaunchKernelGGL((k_wgrad<BF, SA, SB>), dim3(grid), dim3(bwd::kThreads), 0, c.st, a, b, M, \
+#define TSDFS_WGRAD(PM, SA, SB)                                                            \
+    hipLaunchKernelGGL((k_wgrad<PM, SA, SB>), dim3(grid), dim3(bwd::kThreads), 0, c.st, a, b, M, \
                        N, R, kc, n_mt, n_nt, n_ch, c.part, bp)
-    if (!c.bf16)
-        TSDFS_WGRAD(false, float, float);
+    if (c.split)
+        TSDFS_WGRAD(bwd::kSplit, float, float);
+    else if (!c.bf16)
+        TSDFS_WGRAD(bwd::kF32, float, float);
     else if (a_bf && b_bf)
-        TSDFS_WGRAD(true, __bf16, __bf16);
+        TSDFS_WGRAD(bwd::kBf16, __bf16, __bf16);
     else if (a_bf)
-        TSDFS_WGRAD(true, __bf16, float);
+        TSDFS_WGRAD(bwd::kBf16, __bf16, float);
     else if (b_bf)
-        TSDFS_WGRAD(true, float, __bf16);
+        TSDFS_WGRAD(bwd::kBf16, float, __bf16);
     else
-        TSDFS_WGRAD(true, float, float);
+        TSDFS_WGRAD(bwd::kBf16, float, float);
 #undef TSDFS_WGRAD
     const int mn = M * N;
     hipLaunchKernelGGL(k_chunk_reduce, dim3((unsigned)((mn + 255) / 256)), dim3(256), 0, c.st,
@@ -594,13 +601,13 @@ static int network_backward(const tsdfs_field *F, const float *o, const float *v
                             const int32_t *ray_id, int64_t S, const float *eik_x, int64_t P,
                             float eik_lambda, const float *d_f, const float *d_grad,
                             const float *d_rgb, float *gs, float *gc, char *ws, hipStream_t st,
-                            float *eik_loss_out, bool bf16) {
+                            float *eik_loss_out, bool bf16, bool split) {
     const int R = (int)(S + P);
     BwdBufs B;
     carve(B, F, R, ws);
     B.S = (int)S;
     B.P = (int)P;
-    const Ctx C{st, bf16, B.splitk, B.splitk_cap, B.bpart};
+    const Ctx C{st, bf16, B.splitk, B.splitk_cap, B.bpart, split};
     const tsdfs_field_desc &d = F->desc;
     const int W = d.width, nh = d.n_hidden, dg = B.dg, ldg = B.ldg, cin = B.cin, ldc = B.ldc;
     const int nf = d.n_feat, ny = B.ny, ldy = B.ldy;
@@ -1005,7 +1012,7 @@ int sdf_mlp_bwd(const tsdfs_field *F, const float *o, const float *v, const floa
     TSDFS_CHECK_ARG(F != nullptr, "field is NULL");
     TSDFS_CHECK_ARG(n_samples >= 0 && n_eik >= 0, "negative sizes");
     TSDFS_CHECK_ARG(n_samples + n_eik < kMaxBwdRows, "too many rows");
-    if (precision != TSDFS_FP32 && precision != TSDFS_BF16) {
+    if (precision != TSDFS_FP32 && precision != TSDFS_BF16 && precision != TSDFS_BF16X6) {
         set_error("sdf_mlp_bwd: precision %d not supported", precision);
         return TSDFS_EUNSUPPORTED;
     }
@@ -1019,7 +1026,8 @@ int sdf_mlp_bwd(const tsdfs_field *F, const float *o, const float *v, const floa
                     "workspace too small or not 256-byte aligned (%zu < %zu)", ws_bytes, need);
     return network_backward(F, o, v, t, ray_id, n_samples, eik_x, n_eik, eik_lambda, d_f,
                             d_grad_f, d_rgb, d_params_sdf, d_params_color, (char *)ws,
-                            as_stream(stream), eik_loss, precision == TSDFS_BF16);
+                            as_stream(stream), eik_loss, precision == TSDFS_BF16,
+                            precision == TSDFS_BF16X6);
 }
 
 // Adam (the optimiser of the NeuS-family training the paper builds on):

@@ -374,9 +374,10 @@ class Field:
 
     def backward(self, o, v, t, ray_id, d_f, d_grad, d_rgb, eik_x=None, eik_lambda=0.0,
                  d_sdf=None, d_col=None, precision=L.FP32):
-        """Accumulate weight gradients (FP32 outputs; products in FP32 or with
-        BF16 inputs) into d_sdf / d_col (allocated zeroed when None); returns
-        (d_sdf, d_col, eikonal loss tensor)."""
+        """Accumulate weight gradients (FP32 outputs; products in FP32, with
+        BF16 inputs, or with FP32 operands as three-part BF16 products) into
+        d_sdf / d_col (allocated zeroed when None); returns (d_sdf, d_col,
+        eikonal loss tensor)."""
         d = _dev()
         S = t.shape[0] if t is not None else 0
         P = eik_x.shape[0] if eik_x is not None else 0

@@ -114,10 +114,9 @@ def test_device_sample_count(prec):
             assert bool(torch.isnan(a[m:]).all()), (prec, count)
 
 
-def test_split_precision_is_forward_only():
-    """The three-part BF16 products are a forward mode: sdf_mlp_bwd refuses
-    them (TSDFS_EUNSUPPORTED), as it refuses any unknown precision value, and
-    so does sdf_mlp_fwd for a value past the last mode."""
+def test_unknown_precision_is_refused():
+    """sdf_mlp_fwd and sdf_mlp_bwd refuse a precision value past the last
+    mode (TSDFS_EUNSUPPORTED)."""
     from paper_2311_17878_amd import _lib as L
     cfg = get_config("c1")
     o, v, t, rid = samples(cfg, 64, seed=3)
@@ -129,5 +128,5 @@ def test_split_precision_is_forward_only():
     f, g, rgb = F.forward(*args, precision=L.BF16X6)
     with pytest.raises(L.TsdfsError) as e:
         F.backward(*args, d_f=torch.ones_like(f), d_grad=torch.zeros_like(g),
-                   d_rgb=torch.zeros_like(rgb), precision=L.BF16X6)
+                   d_rgb=torch.zeros_like(rgb), precision=L.BF16X6 + 1)
     assert e.value.code == L.TSDFS_EUNSUPPORTED

@@ -28,7 +28,8 @@ def make_field(cfg, sdf_params=None, color_params=None):
 def test_repack_equals_packing_at_creation(name):
     """Repacking unchanged parameters changes nothing; parameters changed in
     place and repacked give bit for bit the outputs of a field created from
-    the changed parameters, FP32 and BF16."""
+    the changed parameters, FP32, BF16 and FP32 operands as three-part BF16
+    products (whose weight copies the repack splits anew)."""
     from paper_2311_17878_amd import _lib as L
     cfg = get_config(name)
     rng = np.random.default_rng(5)
@@ -40,9 +41,10 @@ def test_repack_equals_packing_at_creation(name):
     rid = np.arange(n, dtype=np.int32)
     args = (dev(o), dev(v), dev(t), dev(rid))
     F = make_field(cfg)
-    before = {p: [x.clone() for x in F.forward(*args, precision=p)] for p in (L.FP32, L.BF16)}
+    precs = (L.FP32, L.BF16, L.BF16X6)
+    before = {p: [x.clone() for x in F.forward(*args, precision=p)] for p in precs}
     F.repack()
-    for p in (L.FP32, L.BF16):
+    for p in precs:
         for a, b in zip(before[p], F.forward(*args, precision=p)):
             assert torch.equal(a, b)
     # change every parameter in place, repack, compare with a fresh field
@@ -55,7 +57,7 @@ def test_repack_equals_packing_at_creation(name):
     view.mul_(float(scale))
     F.repack()
     G = make_field(cfg, sp * scale, cp * scale)
-    for p in (L.FP32, L.BF16):
+    for p in precs:
         for a, b in zip(F.forward(*args, precision=p), G.forward(*args, precision=p)):
             assert torch.equal(a, b)
 
@@ -83,7 +85,7 @@ def test_adam_step_matches_oracle():
     assert (np.abs(vd.cpu().numpy() - vr) <= 1e-6 * gmax * gmax).all()
 
 
-@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+@pytest.mark.parametrize("prec", ["fp32", "bf16", "bf16x6"])
 def test_training_loop_lowers_the_loss(prec):
     """Twenty TSDF-bounded steps on one fixed batch of the small scene (Adam,
     lr 1e-3): the photometric loss falls, the eikonal term stays finite."""
@@ -100,7 +102,7 @@ def test_training_loop_lowers_the_loss(prec):
     bo, bv, target = cfg.training_batch(2048, seed=3)
     eik = cfg.eikonal_points(2048, seed=3)
     batch = (dev(bo), dev(bv), dev(target), dev(eik))
-    precision = L.FP32 if prec == "fp32" else L.BF16
+    precision = {"fp32": L.FP32, "bf16": L.BF16, "bf16x6": L.BF16X6}[prec]
     hist, opt = train(R, lambda k: batch, 20, precision=precision, opt=Adam(R.field, lr=1e-3))
     losses = [a for a, _ in hist]
     print("%s loop: rgb loss %.5f -> %.5f, eikonal %.4f -> %.4f"
