@@ -8,6 +8,7 @@ and the FP32 outputs must match the FP64 oracle.  The device-side sample
 count is checked below, at and above the capacity: entries past it are left
 untouched."""
 import ctypes
+import dataclasses
 
 import numpy as np
 import pytest
@@ -130,3 +131,36 @@ def test_unknown_precision_is_refused():
         F.backward(*args, d_f=torch.ones_like(f), d_grad=torch.zeros_like(g),
                    d_rgb=torch.zeros_like(rgb), precision=L.BF16X6 + 1)
     assert e.value.code == L.TSDFS_EUNSUPPORTED
+
+
+@pytest.mark.parametrize("width", [96, 160, 224])
+@pytest.mark.parametrize("prec", PRECISIONS)
+def test_other_widths(width, prec):
+    """Networks of other supported widths (3, 5 and 7 row tiles per layer,
+    each kernel's other work shares), a 2-frequency encoding and a skip
+    layer at 2: FP32 products and FP32 operands as three-part BF16 products
+    against the FP64 oracle; BF16 products bit-identical between a ragged
+    launch and the same samples inside a larger one."""
+    from paper_2311_17878_amd import _lib as L
+    from synth.weights import SdfNet, ColorNet
+    base = get_config("c2")
+    cfg = dataclasses.replace(
+        base, sdf=SdfNet(width=width, n_hidden=5, pe_freqs=2, skip_at=2, n_feat=width,
+                         inside_out=True),
+        color=ColorNet(width=width, n_hidden=2, n_feat=width))
+    precision = _precision(L, prec)
+    o, v, t, rid = samples(cfg, 700, seed=21)
+    F = make_field(cfg)
+    od, vd = dev(o), dev(v)
+    big = [x.clone() for x in F.forward(od, vd, dev(t), dev(rid), precision=precision)]
+    sl = slice(37, 37 + 259)
+    part = F.forward(od, vd, dev(t[sl]), dev(rid[sl]), precision=precision)
+    for a, b in zip(part, big):
+        assert torch.equal(a, b[sl])
+    if prec != "bf16":
+        of, og, orgb = OF.eval_samples(cfg, cfg.sdf_params(), cfg.color_params(), o, v, t, rid)
+        ef = np.abs(host(big[0]) - of).max()
+        eg = np.abs(host(big[1]) - og).max()
+        ec = np.abs(host(big[2]) - orgb).max()
+        print("width %d %s: max abs err f %.3g grad %.3g rgb %.3g" % (width, prec, ef, eg, ec))
+        assert ef <= 1e-4 and eg <= 2e-4 and ec <= 2e-5
