@@ -400,7 +400,7 @@ int composite(const int32_t *offsets, int64_t n_rays, const float *v, const floa
  * and d_rgb [S,3].  Depth and normal are normalised by acc, so their
  * adjoints are zero for rays with acc = 0 (where both outputs are 0).  The
  * sample positions t are inputs, not differentiated.  Inputs as in
- * composite(); one thread per ray, deterministic.
+ * composite(); a group of 16 lanes per ray, deterministic.
  *
  * rgb_loss: loss = (1/B) sum_rays |rgb - target|^2 (device scalar, written
  * by the call; summed by one workgroup in a fixed order, so its bits do not

@@ -130,103 +130,165 @@ namespace tsdfs {
 
 __device__ __forceinline__ float sigm(float x) { return 1.0f / (1.0f + expf(-x)); }
 
-// Adjoint of k_composite for all four outputs, one thread per ray (training
-// batches are small next to a render).  With w_i = T_i alpha_i and the
-// per-sample value e_i = dC.c_i + dA + (dD (t_i - D) + dN.(n_i - N)) / acc
-// (the depth and normal terms vanish when acc = 0), the adjoint of
-// L_j = log(1 - alpha_j) is  -T_{j+1} e_j + sum_{i>j} w_i e_i.  A first pass
-// rebuilds acc, D and N, the second one walks the samples in order.
-__global__ void k_composite_bwd(const int32_t *__restrict__ offsets, int64_t n_rays,
-                                const float *__restrict__ v, const float *__restrict__ t,
-                                const float *__restrict__ dt, const float *__restrict__ f,
-                                const float *__restrict__ g, const float *__restrict__ rgb, float s,
-                                const float *__restrict__ d_rgb_out,
-                                const float *__restrict__ d_depth_out,
-                                const float *__restrict__ d_normal_out,
-                                const float *__restrict__ d_acc_out, float *__restrict__ d_f,
-                                float *__restrict__ d_g, float *__restrict__ d_rgb) {
-    const int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (r >= n_rays) return;
-    const int32_t j0 = offsets[r], j1 = offsets[r + 1];
-    const float vx = v[3 * r], vy = v[3 * r + 1], vz = v[3 * r + 2];
-    float dC[3] = {0.f, 0.f, 0.f}, dN[3] = {0.f, 0.f, 0.f};
-    if (d_rgb_out)
-        for (int a = 0; a < 3; ++a) dC[a] = d_rgb_out[3 * r + a];
-    if (d_normal_out)
-        for (int a = 0; a < 3; ++a) dN[a] = d_normal_out[3 * r + a];
-    const float dD = d_depth_out ? d_depth_out[r] : 0.0f;
-    const float dA = d_acc_out ? d_acc_out[r] : 0.0f;
+// inclusive sum over the lanes of a 16-lane group up to this one
+__device__ __forceinline__ float group_scan(float x, int sub) {
+#pragma unroll
+    for (int d = 1; d < kCGroup; d <<= 1) {
+        const float y = __shfl_up(x, d, kCGroup);
+        if (sub >= d) x += y;
+    }
+    return x;
+}
+
+__device__ __forceinline__ float group_sum(float x) {
+#pragma unroll
+    for (int d = kCGroup / 2; d >= 1; d >>= 1) x += __shfl_xor(x, d, kCGroup);
+    return x;
+}
+
+// Adjoint of k_composite for all four outputs, a group of 16 lanes per ray
+// walking its samples 16 at a time, as k_composite does.  With
+// w_i = T_i alpha_i and the per-sample value
+// e_i = dC.c_i + dA + (dD (t_i - D) + dN.(n_i - N)) / acc (the depth and
+// normal terms vanish when acc = 0), the adjoint of L_j = log(1 - alpha_j)
+// is  -T_{j+1} e_j + sum_{i>j} w_i e_i.  A first pass rebuilds acc, D and N
+// (16-lane sums), the second forms the prefix sums of w_i e_i with a group
+// scan per chunk plus the running total of the earlier chunks.  Per sample
+// the arithmetic is that of the sequential form; only the order of the sums
+// differs (rounding level).
+__global__ void __launch_bounds__(256) k_composite_bwd(
+    const int32_t *__restrict__ offsets, int64_t n_rays, const float *__restrict__ v,
+    const float *__restrict__ t, const float *__restrict__ dt, const float *__restrict__ f,
+    const float *__restrict__ g, const float *__restrict__ rgb, float s,
+    const float *__restrict__ d_rgb_out, const float *__restrict__ d_depth_out,
+    const float *__restrict__ d_normal_out, const float *__restrict__ d_acc_out,
+    float *__restrict__ d_f, float *__restrict__ d_g, float *__restrict__ d_rgb) {
+    const int64_t r = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / kCGroup;
+    const int sub = threadIdx.x % kCGroup;
+    // a group past the last ray runs no chunk (j0 = j1 = 0) but takes part
+    // in the group-wide shuffles like the others
+    const bool ray = r < n_rays;
+    int32_t j0 = 0, j1 = 0;
+    float vx = 0.f, vy = 0.f, vz = 0.f;
+    float dC[3] = {0.f, 0.f, 0.f}, dN[3] = {0.f, 0.f, 0.f}, dD = 0.0f, dA = 0.0f;
+    if (ray) {
+        j0 = offsets[r];
+        j1 = offsets[r + 1];
+        vx = v[3 * r];
+        vy = v[3 * r + 1];
+        vz = v[3 * r + 2];
+        if (d_rgb_out)
+            for (int a = 0; a < 3; ++a) dC[a] = d_rgb_out[3 * r + a];
+        if (d_normal_out)
+            for (int a = 0; a < 3; ++a) dN[a] = d_normal_out[3 * r + a];
+        dD = d_depth_out ? d_depth_out[r] : 0.0f;
+        dA = d_acc_out ? d_acc_out[r] : 0.0f;
+    }
 
     // pass 1: acc, sum w t, sum w n_hat, sum w (dC.c)
-    float logT = 0.0f, acc = 0.0f, P = 0.0f, Sc = 0.0f, Q[3] = {0.f, 0.f, 0.f};
-    for (int32_t j = j0; j < j1; ++j) {
-        const float gx = g[3 * j], gy = g[3 * j + 1], gz = g[3 * j + 2];
-        const float cosv = fminf(vx * gx + vy * gy + vz * gz, 0.0f);
-        const float half = 0.5f * cosv * dt[j];
-        const float L = fminf(logsig(s * (f[j] + half)) - logsig(s * (f[j] - half)), 0.0f);
-        const float w = expf(logT) * (-expm1f(L));
-        acc += w;
-        P = fmaf(w, t[j], P);
-        Sc += w * (dC[0] * rgb[3 * j] + dC[1] * rgb[3 * j + 1] + dC[2] * rgb[3 * j + 2]);
-        const float gn = sqrtf(gx * gx + gy * gy + gz * gz);
-        if (gn > 0.0f) {
-            const float k = w / gn;
-            Q[0] = fmaf(k, gx, Q[0]);
-            Q[1] = fmaf(k, gy, Q[1]);
-            Q[2] = fmaf(k, gz, Q[2]);
+    float carry = 0.0f, acc = 0.0f, P = 0.0f, Sc = 0.0f, Q[3] = {0.f, 0.f, 0.f};
+    for (int32_t base = j0; base < j1; base += kCGroup) {
+        const int32_t j = base + sub;
+        const bool live = j < j1;
+        float L = 0.0f;
+        if (live) {
+            const float gx = g[3 * j], gy = g[3 * j + 1], gz = g[3 * j + 2];
+            const float cosv = fminf(vx * gx + vy * gy + vz * gz, 0.0f);
+            const float half = 0.5f * cosv * dt[j];
+            L = fminf(logsig(s * (f[j] + half)) - logsig(s * (f[j] - half)), 0.0f);
         }
-        logT += L;
+        const float inc = group_scan(L, sub);
+        const float total = __shfl(inc, kCGroup - 1, kCGroup);
+        if (live) {
+            const float gx = g[3 * j], gy = g[3 * j + 1], gz = g[3 * j + 2];
+            const float w = expf(carry + (inc - L)) * (-expm1f(L));
+            acc += w;
+            P = fmaf(w, t[j], P);
+            Sc += w * (dC[0] * rgb[3 * j] + dC[1] * rgb[3 * j + 1] + dC[2] * rgb[3 * j + 2]);
+            const float gn = sqrtf(gx * gx + gy * gy + gz * gz);
+            if (gn > 0.0f) {
+                const float k = w / gn;
+                Q[0] = fmaf(k, gx, Q[0]);
+                Q[1] = fmaf(k, gy, Q[1]);
+                Q[2] = fmaf(k, gz, Q[2]);
+            }
+        }
+        carry += total;
     }
+    acc = group_sum(acc);
+    P = group_sum(P);
+    Sc = group_sum(Sc);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) Q[a] = group_sum(Q[a]);
     const float ia = acc > 0.0f ? 1.0f / acc : 0.0f;
     const float D = P * ia;
     const float N[3] = {Q[0] * ia, Q[1] * ia, Q[2] * ia};
     const float dDa = dD * ia;
     const float dNa[3] = {dN[0] * ia, dN[1] * ia, dN[2] * ia};
     // sum_i w_i e_i (the depth and normal parts sum to zero up to rounding)
-    const float total = Sc + dA * acc + dDa * (P - D * acc) +
-                        dNa[0] * (Q[0] - N[0] * acc) + dNa[1] * (Q[1] - N[1] * acc) +
-                        dNa[2] * (Q[2] - N[2] * acc);
+    const float total_we = Sc + dA * acc + dDa * (P - D * acc) +
+                           dNa[0] * (Q[0] - N[0] * acc) + dNa[1] * (Q[1] - N[1] * acc) +
+                           dNa[2] * (Q[2] - N[2] * acc);
     const float off_dn = dNa[0] * N[0] + dNa[1] * N[1] + dNa[2] * N[2];
 
-    // pass 2: per-sample adjoints in ray order
-    logT = 0.0f;
-    float done = 0.0f;   // sum_{i<=j} w_i e_i
-    for (int32_t j = j0; j < j1; ++j) {
-        const float gx = g[3 * j], gy = g[3 * j + 1], gz = g[3 * j + 2];
-        const float cv = vx * gx + vy * gy + vz * gz;
-        const float cosv = fminf(cv, 0.0f);
-        const float fj = f[j], dtj = dt[j];
-        const float half = 0.5f * cosv * dtj;
-        const float xn = s * (fj + half), xp = s * (fj - half);
-        const float L = fminf(logsig(xn) - logsig(xp), 0.0f);
-        const float T = expf(logT);
+    // pass 2: per-sample adjoints; done = sum_{i<=j} w_i e_i
+    carry = 0.0f;
+    float done_carry = 0.0f;
+    for (int32_t base = j0; base < j1; base += kCGroup) {
+        const int32_t j = base + sub;
+        const bool live = j < j1;
+        float L = 0.0f, we = 0.0f;
+        float gx = 0.f, gy = 0.f, gz = 0.f, cv = 0.f, dtj = 0.f, xn = 0.f, xp = 0.f, e = 0.f;
+        if (live) {
+            gx = g[3 * j];
+            gy = g[3 * j + 1];
+            gz = g[3 * j + 2];
+            cv = vx * gx + vy * gy + vz * gz;
+            const float cosv = fminf(cv, 0.0f);
+            dtj = dt[j];
+            const float fj = f[j];
+            const float half = 0.5f * cosv * dtj;
+            xn = s * (fj + half);
+            xp = s * (fj - half);
+            L = fminf(logsig(xn) - logsig(xp), 0.0f);
+        }
+        const float inc = group_scan(L, sub);
+        const float total = __shfl(inc, kCGroup - 1, kCGroup);
+        const float T = expf(carry + (inc - L));
         const float alpha = -expm1f(L);
         const float w = T * alpha;
         const float gn = sqrtf(gx * gx + gy * gy + gz * gz);
         const float ig = gn > 0.0f ? 1.0f / gn : 0.0f;
         const float nh[3] = {gx * ig, gy * ig, gz * ig};
-        const float e = dC[0] * rgb[3 * j] + dC[1] * rgb[3 * j + 1] + dC[2] * rgb[3 * j + 2] + dA +
-                        dDa * (t[j] - D) + (dNa[0] * nh[0] + dNa[1] * nh[1] + dNa[2] * nh[2]) -
-                        off_dn;
-        done += w * e;
-        const float dL = -(1.0f - alpha) * T * e + (total - done);
-        // L = logsig(xn) - logsig(xp), d logsig(x)/dx = sigmoid(-x)
-        const float dfn = s * dL * sigm(-xn), dfp = -s * dL * sigm(-xp);
-        d_f[j] = dfn + dfp;
-        const float dcos = (dfn - dfp) * 0.5f * dtj;
-        // d min(cv, 0) / d cv: 1 for cv <= 0 (at the kink cv = 0 the
-        // one-sided derivative from below)
-        const float dcv = cv <= 0.0f ? dcos : 0.0f;
-        // normal: d n_hat = w dN / acc, through n_hat = g / |g|
-        const float pr = dNa[0] * nh[0] + dNa[1] * nh[1] + dNa[2] * nh[2];
-        const float kn = w * ig;
-        d_g[3 * j] = dcv * vx + kn * (dNa[0] - pr * nh[0]);
-        d_g[3 * j + 1] = dcv * vy + kn * (dNa[1] - pr * nh[1]);
-        d_g[3 * j + 2] = dcv * vz + kn * (dNa[2] - pr * nh[2]);
-        d_rgb[3 * j] = w * dC[0];
-        d_rgb[3 * j + 1] = w * dC[1];
-        d_rgb[3 * j + 2] = w * dC[2];
-        logT += L;
+        if (live) {
+            e = dC[0] * rgb[3 * j] + dC[1] * rgb[3 * j + 1] + dC[2] * rgb[3 * j + 2] + dA +
+                dDa * (t[j] - D) + (dNa[0] * nh[0] + dNa[1] * nh[1] + dNa[2] * nh[2]) - off_dn;
+            we = w * e;
+        }
+        const float done_inc = group_scan(we, sub);
+        const float done_total = __shfl(done_inc, kCGroup - 1, kCGroup);
+        if (live) {
+            const float done = done_carry + done_inc;
+            const float dL = -(1.0f - alpha) * T * e + (total_we - done);
+            // L = logsig(xn) - logsig(xp), d logsig(x)/dx = sigmoid(-x)
+            const float dfn = s * dL * sigm(-xn), dfp = -s * dL * sigm(-xp);
+            d_f[j] = dfn + dfp;
+            const float dcos = (dfn - dfp) * 0.5f * dtj;
+            // d min(cv, 0) / d cv: 1 for cv <= 0 (at the kink cv = 0 the
+            // one-sided derivative from below)
+            const float dcv = cv <= 0.0f ? dcos : 0.0f;
+            // normal: d n_hat = w dN / acc, through n_hat = g / |g|
+            const float pr = dNa[0] * nh[0] + dNa[1] * nh[1] + dNa[2] * nh[2];
+            const float kn = w * ig;
+            d_g[3 * j] = dcv * vx + kn * (dNa[0] - pr * nh[0]);
+            d_g[3 * j + 1] = dcv * vy + kn * (dNa[1] - pr * nh[1]);
+            d_g[3 * j + 2] = dcv * vz + kn * (dNa[2] - pr * nh[2]);
+            d_rgb[3 * j] = w * dC[0];
+            d_rgb[3 * j + 1] = w * dC[1];
+            d_rgb[3 * j + 2] = w * dC[2];
+        }
+        carry += total;
+        done_carry += done_total;
     }
 }
 
@@ -268,9 +330,9 @@ extern "C" int composite_bwd(const int32_t *offsets, int64_t n_rays, const float
     if (n_rays == 0) return TSDFS_OK;
     TSDFS_CHECK_ARG(offsets && v && t && dt && f && grad_f && rgb && d_f && d_grad_f && d_rgb,
                     "NULL array argument");
-    hipLaunchKernelGGL(k_composite_bwd, dim3((unsigned)((n_rays + 255) / 256)), dim3(256), 0,
-                       as_stream(stream), offsets, n_rays, v, t, dt, f, grad_f, rgb, s, d_out_rgb,
-                       d_out_depth, d_out_normal, d_out_acc, d_f, d_grad_f, d_rgb);
+    hipLaunchKernelGGL(k_composite_bwd, dim3((unsigned)((n_rays * kCGroup + 255) / 256)), dim3(256),
+                       0, as_stream(stream), offsets, n_rays, v, t, dt, f, grad_f, rgb, s,
+                       d_out_rgb, d_out_depth, d_out_normal, d_out_acc, d_f, d_grad_f, d_rgb);
     TSDFS_LAUNCH_CHECK();
     return TSDFS_OK;
 }
