@@ -311,7 +311,7 @@ int scatter_rays(const int32_t *idx, const int64_t *n_sel_dev, int64_t cap, cons
  * [y0, feat]; f = scale*y0 in metres; grad f = d f/d p.  Colour network:
  * [x_hat, v, grad f, feat] -> ReLU hidden layers -> sigmoid(3).
  * Parameters (host FP32): per linear layer W [out][in] row-major then b.
- * Supported shapes: width 64 or 256 (multiple of 32), <= 8 SDF hidden
+ * Supported shapes: width a multiple of 32 from 64 to 256, <= 8 SDF hidden
  * layers, <= 4 colour hidden layers, feat = width. */
 typedef struct {
     int32_t width;       /* hidden width of both networks */
