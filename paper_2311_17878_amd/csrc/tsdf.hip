@@ -869,7 +869,10 @@ int tsdf_ray_bounds(const tsdfs_grid *grid, const uint8_t *flags, const float *o
     if (n_rays == 0) return TSDFS_OK;
     TSDFS_CHECK_ARG(flags && o && v && t_n && t_f && first_hit && n_vox_out && status,
                     "NULL array argument");
-    hipLaunchKernelGGL(k_bounds, dim3(blocks_for(n_rays, 256)), dim3(256), 0, as_stream(stream),
+    // one wave per workgroup: a small batch (a training step's 8192 rays)
+    // spreads over 128 compute units instead of 32, and its walks, bound by
+    // the dependent arithmetic of their steps, end sooner
+    hipLaunchKernelGGL(k_bounds, dim3(blocks_for(n_rays, 64)), dim3(64), 0, as_stream(stream),
                        g, flags, o, v, n_rays, t_far, t_n, t_f, first_hit, n_vox_out, status,
                        n_steps);
     TSDFS_LAUNCH_CHECK();
