@@ -598,6 +598,8 @@ __global__ void __launch_bounds__(kBrickBlock) k_brick_place(const uint32_t *__r
 
 // --------------------------------------------------------------- bounds ----
 
+constexpr int kAhead = 4;   // voxels the bounds walk runs ahead of its visits
+
 __global__ void __launch_bounds__(256) k_bounds(LatGrid g, const uint8_t *__restrict__ flags,
                                                 const float *__restrict__ o,
                                                 const float *__restrict__ v, int64_t n_rays,
@@ -621,66 +623,84 @@ __global__ void __launch_bounds__(256) k_bounds(LatGrid g, const uint8_t *__rest
         int32_t inn, ind, outn, outd;
         Walk w;
         if (grid_range(g, r, inn, ind, outn, outd) && walk_begin(g, r, inn, ind, w)) {
-            // The flags of the next voxel are loaded before the current one is
-            // tested (the walk does not depend on them), so two loads are in
-            // flight per step.  A voxel is visited while its FP32 entry
-            // parameter is below t_far (no division when t_far is infinite).
+            // A voxel is visited while its FP32 entry parameter is below t_far
+            // (no division when t_far is infinite).  The walk does not depend
+            // on the flags, so it runs kAhead - 1 voxels ahead of the visits
+            // and its results wait in a ring of registers: slot j holds, for
+            // the voxel at position p % kAhead == j along the walk, whether the
+            // walk reached it, its linear index, its flags (the load in
+            // flight) and the parameter where the walk leaves it.  Phase 1
+            // looks for the first voxel of the surface group; phase 2, from
+            // that voxel on, counts the run of voxels whose neighbourhood is
+            // all inside.
             const bool far_limit = !(t_far == INFINITY);   // NaN: no voxel is below it
             auto before_far = [&](const Walk &x) __attribute__((always_inline)) {
                 return !far_limit || tau_f32(x.en_num, x.en_den) < t_far;
             };
-            auto flag_of = [&](const Walk &x, bool valid) __attribute__((always_inline)) {
-                return flags[valid ? vox_linear(g, x.i) : 0];   // in bounds either way
+            Walk ahd = w;
+            bool aok = before_far(ahd);
+            bool s_ok[kAhead];
+            int32_t s_lin[kAhead], s_xn[kAhead], s_xd[kAhead];
+            uint8_t s_fl[kAhead];
+            // the walk's next voxel into slot j (it stays put once it has left
+            // the grid or passed t_far); the exit of the voxel it leaves goes
+            // to the slot before
+            auto produce = [&](int j) __attribute__((always_inline)) {
+                int32_t xn = 0, xd = 1;
+                if (aok)
+                    aok = walk_step_reg(g, ahd, exit_axis_reg(ahd), xn, xd) && before_far(ahd);
+                s_xn[(j + kAhead - 1) % kAhead] = xn;
+                s_xd[(j + kAhead - 1) % kAhead] = xd;
+                s_ok[j] = aok;
+                s_lin[j] = aok ? (int32_t)vox_linear(g, ahd.i) : 0;
+                s_fl[j] = flags[s_lin[j]];   // in bounds either way
             };
-            Walk cur = w, nxt;
-            bool ok = before_far(cur);
-            uint8_t fc = flag_of(cur, ok);
-            // phase 1: first voxel of the surface group
-            bool found = false;
-            while (ok) {
-                ++steps;
-                nxt = cur;
-                int32_t xn, xd;
-                const bool nok =
-                    walk_step_reg(g, nxt, exit_axis_reg(nxt), xn, xd) && before_far(nxt);
-                const uint8_t fn = flag_of(nxt, nok);
-                if (fc & 1u) {
-                    found = true;
-                    break;
-                }
-                cur = nxt;
-                fc = fn;
-                ok = nok;
-            }
-            if (found) {
-                fh = (int32_t)vox_linear(g, cur.i);
-                tn = tau_f32(cur.en_num, cur.en_den);
-                st = TSDFS_NO_FAR;
-                int m = 0;
-                int32_t ex_num = cur.en_num, ex_den = cur.en_den;   // exit of the last voxel
-                bool first = true;
-                while (ok) {
-                    if (!first) ++steps;
-                    first = false;
-                    ++nv;
-                    nxt = cur;
-                    const bool nok =
-                        walk_step_reg(g, nxt, exit_axis_reg(nxt), ex_num, ex_den) && before_far(nxt);
-                    const uint8_t fn = flag_of(nxt, nok);
-                    m = (fc & 2u) ? m + 1 : 0;
-                    if (m == g.M) {
-                        tf = tau_f32(ex_num, ex_den);
-                        st = TSDFS_HIT;
-                        break;
+            s_ok[0] = aok;
+            s_lin[0] = aok ? (int32_t)vox_linear(g, ahd.i) : 0;
+            s_fl[0] = flags[s_lin[0]];
+#pragma unroll
+            for (int j = 1; j < kAhead; ++j) produce(j);
+            bool alive = true, found = false;
+            int m = 0;
+            int32_t en_num = w.en_num, en_den = w.en_den;   // entry of the visited voxel
+            int32_t ex_num = 0, ex_den = 1;   // exit of the last voxel of phase 2
+            // visit the voxel of slot j, then refill the slot with the voxel
+            // kAhead positions on (outside every branch, so that each slot is
+            // written only by its own load and the loads stay in flight)
+            auto visit = [&](int j) __attribute__((always_inline)) {
+                alive = alive && s_ok[j];
+                if (alive) {
+                    ++steps;   // once per voxel: phase 2 starts on phase 1's last
+                    const uint8_t fc = s_fl[j];
+                    if (!found && (fc & 1u)) {
+                        found = true;
+                        fh = s_lin[j];
+                        tn = tau_f32(en_num, en_den);
+                        st = TSDFS_NO_FAR;
                     }
-                    cur = nxt;
-                    fc = fn;
-                    ok = nok;
+                    if (found) {
+                        ++nv;
+                        ex_num = s_xn[j];
+                        ex_den = s_xd[j];
+                        m = (fc & 2u) ? m + 1 : 0;
+                        if (m == g.M) {
+                            tf = tau_f32(ex_num, ex_den);
+                            st = TSDFS_HIT;
+                            alive = false;
+                        }
+                    }
+                    en_num = s_xn[j];
+                    en_den = s_xd[j];
                 }
-                if (st == TSDFS_NO_FAR) {
-                    const float last_exit = tau_f32(ex_num, ex_den);
-                    tf = last_exit < t_far ? last_exit : t_far;
-                }
+                produce(j);
+            };
+            while (alive) {
+#pragma unroll
+                for (int j = 0; j < kAhead; ++j) visit(j);
+            }
+            if (st == TSDFS_NO_FAR) {
+                const float last_exit = tau_f32(ex_num, ex_den);
+                tf = last_exit < t_far ? last_exit : t_far;
             }
         }
     }
@@ -870,8 +890,7 @@ int tsdf_ray_bounds(const tsdfs_grid *grid, const uint8_t *flags, const float *o
     TSDFS_CHECK_ARG(flags && o && v && t_n && t_f && first_hit && n_vox_out && status,
                     "NULL array argument");
     // one wave per workgroup: a small batch (a training step's 8192 rays)
-    // spreads over 128 compute units instead of 32, and its walks, bound by
-    // the dependent arithmetic of their steps, end sooner
+    // spreads over 128 compute units instead of 32
     hipLaunchKernelGGL(k_bounds, dim3(blocks_for(n_rays, 64)), dim3(64), 0, as_stream(stream),
                        g, flags, o, v, n_rays, t_far, t_n, t_f, first_hit, n_vox_out, status,
                        n_steps);
