@@ -526,7 +526,6 @@ struct BwdBufs {
     float *E[kMaxHidden];                 // E_l = delta_{l+1} W_{l+1} (l < n_hidden - 1)
     float *Z2[kMaxHidden];                // second-order contributions
     float *Eg4;                           // skip layer's encoding rows of the reverse pass [R,ldg]
-    float *Y;                             // output layer [R, ldy]
     float *g;                             // grad f [R,3]
     float *Cin;                           // colour input [R, ldc]
     float *Hc[kMaxColor];                 // colour activations [R, W]
@@ -576,7 +575,6 @@ static size_t carve(BwdBufs &b, const tsdfs_field *F, int R, char *base) {
         b.Z2[l] = take((size_t)R * W);
     }
     b.Eg4 = take((size_t)R * b.ldg);
-    b.Y = take((size_t)R * b.ldy);
     b.g = take((size_t)R * 3);
     b.Cin = take((size_t)R * b.ldc);
     for (int l = 0; l < F->desc.col_hidden; ++l) b.Hc[l] = take((size_t)R * W);
@@ -743,12 +741,15 @@ static int network_backward(const tsdfs_field *F, const float *o, const float *v
             });
         }
     }
-    // output layer Y = X_last W_out^T + b_out
+    // output layer Y = X_last W_out^T + b_out, written straight into the
+    // colour input: the features land in its columns 9 .., y0 in column 8,
+    // which the colour input's assembly then fills with the last component
+    // of grad f (y0 itself has no further use here)
     {
         Epi e;
         e.mode = E_BIAS;
-        e.o0 = B.Y;
-        e.ld0 = ldy;
+        e.o0 = B.Cin + 8;
+        e.ld0 = ldc;
         e.bias = bl(nh);
         BWD(gemm_row(C, R, ny, W, B.X[nh], sb, W, B.Wn[nh], ldn(nh), e));
     }
@@ -791,13 +792,9 @@ static int network_backward(const tsdfs_field *F, const float *o, const float *v
     // ---- colour forward
     {
         float *Cin = B.Cin;
-        const float *xh = B.xh, *vr = B.vr, *g = B.g, *Y = B.Y;
-        map2(R, cin, st, [=] __device__(int r, int j) {
-            float x;
-            if (j < 3) x = xh[3 * r + j];
-            else if (j < 6) x = vr[3 * r + j - 3];
-            else if (j < 9) x = g[3 * r + j - 6];
-            else x = Y[(size_t)r * ldy + 1 + (j - 9)];
+        const float *xh = B.xh, *vr = B.vr, *g = B.g;
+        map2(R, 9, st, [=] __device__(int r, int j) {
+            const float x = j < 3 ? xh[3 * r + j] : (j < 6 ? vr[3 * r + j - 3] : g[3 * r + j - 6]);
             Cin[(size_t)r * ldc + j] = x;
         });
     }
