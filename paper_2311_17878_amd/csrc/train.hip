@@ -457,45 +457,89 @@ static int gemm_wgrad(const Ctx &c, int R, int M, int N, const void *A, bool a_b
     return TSDFS_OK;
 }
 
-// y[N] += sum over the rows of row-major A[R,N] (ld): per block of 64
-// columns and chunk of kColsumChunk rows a partial sum (four row phases,
-// coalesced row reads, combined in LDS), then the chunks summed in order,
-// so the result does not depend on scheduling.  part: [ceil(R/chunk)][N].
-constexpr int kColsumChunk = 1024;
+// y[N] += sum over the rows of row-major A[R,N] (ld; N, ld multiples of 4,
+// A 16-byte aligned): per block of 256 columns (a float4 per lane) and
+// chunk of kColsumChunk rows a partial sum (four waves on interleaved rows,
+// four accumulators per lane so that four loads are in flight, combined in
+// a fixed order in LDS), then the chunks summed in order (16 phases per
+// column, combined in a fixed order), so the result does not depend on
+// scheduling.  part: [ceil(R/chunk)][N].
+constexpr int kColsumChunk = 256;
 
 __global__ void __launch_bounds__(256) k_colsum_part(const float *__restrict__ A, int R, int N,
                                                      int ld, float *__restrict__ part) {
-    __shared__ float red[4][64];
+    __shared__ float4 red[4][64];
     const int c = threadIdx.x & 63, ph = threadIdx.x >> 6;
-    const int j = blockIdx.x * 64 + c;
+    const int j = (blockIdx.x * 64 + c) * 4;
     const int64_t r0 = (int64_t)blockIdx.y * kColsumChunk;
     const int64_t r1 = r0 + kColsumChunk < R ? r0 + kColsumChunk : R;
-    float s = 0.0f;
-    if (j < N)
-        for (int64_t r = r0 + ph; r < r1; r += 4) s += A[r * ld + j];
-    red[ph][c] = s;
+    float4 acc[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) acc[u] = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (j < N) {
+        for (int64_t r = r0 + ph; r < r1; r += 16) {
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                if (r + 4 * u < r1) {
+                    const float4 x = *(const float4 *)(A + (r + 4 * u) * ld + j);
+                    acc[u].x += x.x;
+                    acc[u].y += x.y;
+                    acc[u].z += x.z;
+                    acc[u].w += x.w;
+                }
+            }
+        }
+    }
+    float4 t;
+    t.x = (acc[0].x + acc[1].x) + (acc[2].x + acc[3].x);
+    t.y = (acc[0].y + acc[1].y) + (acc[2].y + acc[3].y);
+    t.z = (acc[0].z + acc[1].z) + (acc[2].z + acc[3].z);
+    t.w = (acc[0].w + acc[1].w) + (acc[2].w + acc[3].w);
+    red[ph][c] = t;
     __syncthreads();
-    if (ph == 0 && j < N)
-        part[(int64_t)blockIdx.y * N + j] = (red[0][c] + red[1][c]) + (red[2][c] + red[3][c]);
+    if (ph == 0 && j < N) {
+        const float4 a0 = red[0][c], a1 = red[1][c], a2 = red[2][c], a3 = red[3][c];
+        float4 o;
+        o.x = (a0.x + a1.x) + (a2.x + a3.x);
+        o.y = (a0.y + a1.y) + (a2.y + a3.y);
+        o.z = (a0.z + a1.z) + (a2.z + a3.z);
+        o.w = (a0.w + a1.w) + (a2.w + a3.w);
+        *(float4 *)(part + (int64_t)blockIdx.y * N + j) = o;
+    }
 }
 
-__global__ void k_colsum_fin(const float *__restrict__ part, int n_chunks, int N,
-                             float *__restrict__ y) {
-    const int j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= N) return;
+// y[j] += sum over the chunks, for 64 columns per block: 16 phases of
+// interleaved chunks, combined in a fixed order
+__global__ void __launch_bounds__(1024) k_colsum_fin(const float *__restrict__ part, int n_chunks,
+                                                     int N, float *__restrict__ y) {
+    __shared__ float red[16][64];
+    const int c = threadIdx.x & 63, ph = threadIdx.x >> 6;
+    const int j = blockIdx.x * 64 + c;
     float s = 0.0f;
-    for (int c = 0; c < n_chunks; ++c) s += part[(int64_t)c * N + j];
-    y[j] += s;
+    if (j < N)
+        for (int k = ph; k < n_chunks; k += 16) s += part[(int64_t)k * N + j];
+    red[ph][c] = s;
+    __syncthreads();
+    if (ph == 0 && j < N) {
+        float t = 0.0f;
+#pragma unroll
+        for (int q = 0; q < 16; ++q) t += red[q][c];
+        y[j] += t;
+    }
 }
 
 static int colsum_chunks(int R) { return (R + kColsumChunk - 1) / kColsumChunk; }
 
 static int colsum(hipStream_t st, int R, int N, const float *A, int ld, float *part, float *y) {
     if (R <= 0 || N <= 0) return TSDFS_OK;
+    if (N % 4 || ld % 4 || ((uintptr_t)A & 15)) {
+        set_error("internal: column sums need 16-byte aligned rows");
+        return TSDFS_EHIP;
+    }
     const int nch = colsum_chunks(R);
-    hipLaunchKernelGGL(k_colsum_part, dim3((N + 63) / 64, nch), dim3(256), 0, st, A, R, N, ld,
+    hipLaunchKernelGGL(k_colsum_part, dim3((N + 255) / 256, nch), dim3(256), 0, st, A, R, N, ld,
                        part);
-    hipLaunchKernelGGL(k_colsum_fin, dim3((N + 255) / 256), dim3(256), 0, st, part, nch, N, y);
+    hipLaunchKernelGGL(k_colsum_fin, dim3((N + 63) / 64), dim3(1024), 0, st, part, nch, N, y);
     TSDFS_LAUNCH_CHECK();
     return TSDFS_OK;
 }
