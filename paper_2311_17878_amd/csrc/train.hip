@@ -89,6 +89,7 @@ enum {
     E_MASK,      // o0 = i0 > 0 ? v : 0
     E_SO,        // sp = sigmoid(beta i0): o0 = v sp, o1 = v e beta sp (1 - sp), e = i1 or bias[n]
     E_FO,        // n < split: o0 = s0 v sigmoid(beta i0) + i1
+    E_SPLIT,     // n < split: o0 = v; else o1[n - split] = v on rows r < S, 0 on the others
     E_GRAD       // o0[3 r + a] = sum over n of axis a of (v + i0) i1 (i0 may be NULL)
 };
 
@@ -156,6 +157,11 @@ __device__ __forceinline__ void apply(const Epi &e, int r, int n, float v) {
         const float ee = e.i1 ? e.i1[(unsigned)(r * e.ldi1 + n)] : e.bias[n];
         put<0, BF>(e, e.o0, a0, v * sp);
         put<1, BF>(e, e.o1, (unsigned)(r * e.ld1 + n), v * ee * (e.beta * sp * (1.0f - sp)));
+    } else if constexpr (MODE == E_SPLIT) {
+        if (n < e.split)
+            put<0, BF>(e, e.o0, a0, v);
+        else
+            put<1, BF>(e, e.o1, (unsigned)(r * e.ld1 + (n - e.split)), r < e.S ? v : 0.0f);
     } else {   // E_FO
         if (n < e.split)
             put<0, BF>(e, e.o0, a0,
@@ -230,6 +236,7 @@ __device__ __forceinline__ void epilogue(const Epi &e, const bwd::Acc<RB, CB> &a
         TSDFS_EPI_CASE(E_MASK)
         TSDFS_EPI_CASE(E_SO)
         TSDFS_EPI_CASE(E_FO)
+        TSDFS_EPI_CASE(E_SPLIT)
     }
 #undef TSDFS_EPI_CASE
 }
@@ -896,15 +903,23 @@ static int network_backward(const tsdfs_field *F, const float *o, const float *v
             e.ldi0 = W;
             e.bf_i0 = sb;
         } else {
-            e.o0 = dZn;   // d Cin [R, cin] (ld ldc)
+            // d Cin: its columns 0 .. 8 (x_hat, v, grad f) to dZn (ld ldc), the
+            // feature columns straight into columns 1 .. of Y_bar (the output
+            // layer's adjoint), zero on the eikonal rows
+            e.mode = E_SPLIT;
+            e.o0 = dZn;
             e.ld0 = ldc;
+            e.split = 9;
+            e.o1 = B.Ybar + 1;
+            e.ld1 = ldy;
+            e.S = (int)S;
         }
         BWD(gemm_row(C, R, in, W, dZ, false, W, B.Ct[l], cldt(l), e));
         float *tmp = dZ;
         dZ = dZn;
         dZn = tmp;
     }
-    const float *dCin = dZ;   // [R, cin], ld ldc
+    const float *dCin = dZ;   // columns 0 .. 8 of d Cin, ld ldc
     // ---- g_bar = d grad (samples) + d Cin[:, 6:9] ; eikonal rows
     // 2 lambda (|g| - 1) g / |g| / P ; encoding-space g_bar = J g_bar[axis]
     {
@@ -936,10 +951,10 @@ static int network_backward(const tsdfs_field *F, const float *o, const float *v
     {
         float *Yb = B.Ybar;
         const int Si = (int)S;
-        map2(R, ny, st, [=] __device__(int r, int j) {
-            float y = 0.0f;
-            if (r < Si) y = j == 0 ? (d_f ? scale * d_f[r] : 0.0f) : dCin[(size_t)r * ldc + 9 + (j - 1)];
-            Yb[(size_t)r * ldy + j] = y;
+        // column 0 (d f); the feature columns came from the colour network's
+        // first product
+        map(R, st, [=] __device__(int64_t r) {
+            Yb[r * ldy] = r < Si && d_f ? scale * d_f[r] : 0.0f;
         });
     }
     // ---- second-order pass (adjoint of the reverse pass), forward in l:
