@@ -87,7 +87,7 @@ enum {
     E_RELU,      // o0 = max(v + bias, 0)
     E_RGB,       // c = sigmoid(v + bias): o0 = c, o1 = drgb c (1 - c) for sample rows, else 0
     E_MASK,      // o0 = i0 > 0 ? v : 0
-    E_SO,        // sp = sigmoid(beta i0): o0 = v sp, o1 = v e beta sp (1 - sp), e = i1 or bias[n]
+    E_SO,        // sp = sigmoid(beta i0): o0 = s0 (v sp), o1 = v e beta sp (1 - sp), e = i1 or bias[n]
     E_FO,        // n < split: o0 = s0 v sigmoid(beta i0) + i1
     E_SPLIT,     // n < split: o0 = v; else o1[n - split] = v on rows r < S, 0 on the others
     E_GRAD       // o0[3 r + a] = sum over n of axis a of (v + i0) i1 (i0 may be NULL)
@@ -155,7 +155,7 @@ __device__ __forceinline__ void apply(const Epi &e, int r, int n, float v) {
     } else if constexpr (MODE == E_SO) {
         const float sp = sig_hw(e.beta * e.i0[(unsigned)(r * e.ldi0 + n)]);
         const float ee = e.i1 ? e.i1[(unsigned)(r * e.ldi1 + n)] : e.bias[n];
-        put<0, BF>(e, e.o0, a0, v * sp);
+        put<0, BF>(e, e.o0, a0, e.s0 * (v * sp));
         put<1, BF>(e, e.o1, (unsigned)(r * e.ld1 + n), v * ee * (e.beta * sp * (1.0f - sp)));
     } else if constexpr (MODE == E_SPLIT) {
         if (n < e.split)
@@ -962,14 +962,19 @@ static int network_backward(const tsdfs_field *F, const float *o, const float *v
     // Z2_l = delta_bar E_l sp' (E = w_f on the last layer), delta_bar_{l+1} =
     // E_bar'_l W_{l+1}^T and dW_{l+1} += delta_{l+1}^T E_bar'_l.  E_bar only
     // enters products (BF16 when they are), except the last layer's, whose
-    // column sums give w_f's gradient, and the one below the skip layer,
-    // which is scaled by 1/sqrt2 first (both FP32).
+    // column sums give w_f's gradient (FP32).  The one below the skip layer
+    // goes, scaled by 1/sqrt2, straight into the skip layer's input
+    // [E_bar_l | gbar_g] / sqrt2 (T2).
     auto so_epi = [&](int l, float *Eb) {
         Epi e;
         e.mode = E_SO;
         e.o0 = Eb;
         e.ld0 = W;
-        e.bf_out = (sb && l < nh - 1 && l + 1 != skip) ? 1u : 0u;
+        if (l + 1 == skip) {
+            e.o0 = B.T2;
+            e.s0 = rs2;
+        }
+        e.bf_out = (sb && l < nh - 1) ? 1u : 0u;
         e.o1 = B.Z2[l];
         e.ld1 = W;
         e.i0 = B.Z[l];
@@ -997,16 +1002,17 @@ static int network_backward(const tsdfs_field *F, const float *o, const float *v
         const int inn = F->din[ln], outn = F->dout[ln];
         const float *A = Eb;
         if (ln == skip) {
-            // E_bar'_l = [E_bar_l / sqrt2 | gbar_g / sqrt2]
+            // E_bar'_l = [E_bar_l / sqrt2 | gbar_g / sqrt2]; the first part came
+            // from the product's epilogue
             float *Ep = B.T2;
-            const float *Ebl = Eb, *gbg = B.gbar_g;
-            map2(R, inn, st, [=] __device__(int r, int j) {
-                const unsigned a = (unsigned)(r * W + j);
-                const float x = j < out ? Ebl[a] : gbg[(unsigned)(r * ldg + (j - out))];
+            const float *gbg = B.gbar_g;
+            map2(R, inn - out, st, [=] __device__(int r, int j) {
+                const unsigned a = (unsigned)(r * W + out + j);
+                const float x = rs2 * gbg[(unsigned)(r * ldg + j)];
                 if (sb)
-                    ((__bf16 *)Ep)[a] = (__bf16)(rs2 * x);
+                    ((__bf16 *)Ep)[a] = (__bf16)x;
                 else
-                    Ep[a] = rs2 * x;
+                    Ep[a] = x;
             });
             A = Ep;
         }
